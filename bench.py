@@ -1,0 +1,249 @@
+"""Throughput of full Greek sets on one MI355X.
+
+A step is one whole Greek set of the 5-asset Heston best-of American call
+(25,000 paths x 252 steps, 28 bump-and-revalue scenarios with common random
+numbers, FP32 paths / FP64 regression): path kernel, Gram kernel, backward
+sweep, results back on the host, Greeks.  Inputs are seeded and synthetic.
+
+Printed: one JSON line with the metric (Greek-set path-steps/s), the roofline
+of the dominant kernel (HIP-event times measured on the library's stream),
+the FP64 oracle timed on the host cores over a bounded sample, the accuracy
+of the timed results against the oracle, the plain per-scenario FP64 GPU
+comparator, and p50/p99 request latency of the serving loop under a Poisson
+stream of mixed-size requests.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = "Greek-set path-steps/s at <=1e-4 rel err vs FP64; p50/p99 request latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def per_scenario_models(w):
+    """The bumped models of the Greek set, one per scenario, in the library's
+    scenario order (for the plain per-scenario comparator)."""
+    m, C, opt, b = w["model"], w["corr"], w["option"], w["bumps"]
+    N = len(m["S0"])
+    out = [(m, C, opt)]
+    for sgn in (1.0, -1.0):
+        for a in range(N):
+            mm = dict(m)
+            mm["S0"] = m["S0"].copy()
+            mm["S0"][a] = m["S0"][a] * (1.0 + sgn * b["spot_rel"])
+            out.append((mm, C, opt))
+    for a in range(N):
+        mm = dict(m)
+        mm["v0"] = m["v0"].copy()
+        mm["v0"][a] = m["v0"][a] * (1.0 + b["v0_rel"])
+        out.append((mm, C, opt))
+    out.append((m, C, dict(opt, T=opt["T"] - b["T_abs"])))
+    out.append((dict(m, r=m["r"] + b["r_abs"]), C, opt))
+    for i in range(N):
+        for j in range(i + 1, N):
+            CC = C.copy()
+            CC[i, j] += b["corr_abs"]
+            CC[j, i] += b["corr_abs"]
+            out.append((m, CC, opt))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2206_03719_amd as hs
+
+    hs.lib()
+    torch.cuda.set_device(0)
+    w = W.best_of_call(n_assets=5, n_paths=25000, n_steps=252, precision="fp32")
+    N, P, n = 5, w["n_paths"], w["n_steps"]
+    S = hs.num_scenarios(N, w["bumps"]["mask"])
+    nbytes = hs.workspace_bytes(w["model"], w["option"], P, n, w["bumps"], "fp32")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(timing=False):
+        return hs.price_greeks(w["model"], w["corr"], w["option"], P, n, w["bumps"],
+                               seed=w["seed"], precision="fp32", workspace=ws, stream=stream,
+                               timing=timing)
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        res = step()
+    torch.cuda.synchronize()
+    log("timing %d Greek sets" % args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    path_steps = S * P * n
+    value = path_steps / (ms * 1e-3)
+    log("%.3f ms per Greek set, %.3e path-steps/s" % (ms, value))
+
+    # per-kernel device times (HIP events on the library's stream)
+    kt = {"paths": [], "gram": [], "sweep": []}
+    for _ in range(5):
+        r = step(timing=True)
+        kt["paths"].append(r["t_paths_ms"])
+        kt["gram"].append(r["t_gram_ms"])
+        kt["sweep"].append(r["t_sweep_ms"])
+    kms = {k: float(np.median(v)) for k, v in kt.items()}
+    log("kernel ms (median of 5): %s" % json.dumps(kms))
+    # algorithmic bytes per launch: features are 8 B (FP32 U, A) per path-step;
+    # the path kernel writes them once, the Gram kernel reads dates 1..n-1,
+    # the sweep reads every date once
+    alg = {"paths": S * P * n * 8.0, "gram": S * P * (n - 1) * 8.0, "sweep": S * P * n * 8.0}
+    dom = max(kms, key=kms.get)
+    achieved = alg[dom] / (kms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "kernel_ms": kms,
+                "per_kernel_GBs": {k: round(alg[k] / (kms[k] * 1e-3) / 1e9, 1) for k in kms}}
+
+    out = {"metric": METRIC, "value": value, "unit": "path-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 paths / f64 regression", "data": "synthetic",
+           "config": {"workload": "heston-bestof-call-5x25000x252 greek set (28 scenarios)",
+                      "n_assets": N, "n_paths": P, "n_steps": n, "n_scenarios": S,
+                      "precision": "fp32 paths, fp64 regression", "seed": w["seed"],
+                      "elements_per_s": value * N},
+           "roofline": roofline}
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log("cpu baseline: FP64 oracle, full Greek set, %d threads" % threads)
+        t0 = time.perf_counter()
+        o = oracle.price_greeks(w["model"], w["corr"], w["option"], P, n, w["bumps"], w["seed"],
+                                nthreads=threads)
+        t1 = time.perf_counter()
+        out["cpu_baseline"] = {"value": path_steps / (t1 - t0), "unit": "path-steps/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": "the full 28-scenario Greek set (25k x 252), FP64",
+                               "seconds": t1 - t0}
+        err = np.abs(res["scenario_price"] - o["scenario_price"]) / np.abs(o["scenario_price"])
+        acc = {"max_price_rel_err": float(err.max()),
+               "delta_max_rel_err": float(np.max(np.abs(res["delta"] - o["delta"]) /
+                                                 np.abs(o["delta"])))}
+        out["accuracy_vs_fp64_oracle"] = acc
+        out["valid"] = bool(err.max() <= 1e-4)
+        log("accuracy: %s" % json.dumps(acc))
+
+    if not args.no_comparator:
+        log("comparator: plain per-scenario FP64 launches")
+        models = per_scenario_models(w)
+        nob = dict(w["bumps"], mask=0)
+        wsb = max(hs.workspace_bytes(mm, oo, P, n, nob, "fp64") for mm, _, oo in models)
+        ws64 = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+
+        def plain():
+            return [hs.price_greeks(mm, CC, oo, P, n, nob, seed=w["seed"], precision="fp64",
+                                    workspace=ws64, stream=stream)["price"]
+                    for mm, CC, oo in models]
+        plain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prices = plain()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out["comparator_fp64_per_scenario"] = {
+            "value": path_steps / (t1 - t0), "unit": "path-steps/s", "ms": (t1 - t0) * 1e3,
+            "speedup_of_batched": (t1 - t0) * 1e3 / ms}
+        del ws64
+        log("comparator %.2f ms" % ((t1 - t0) * 1e3))
+
+    if not args.no_serve:
+        out["latency"] = serve_leg(hs, torch, args.serve_requests)
+        log("serving: %s" % json.dumps(out["latency"]))
+
+    print(json.dumps(out), flush=True)
+
+
+def serve_leg(hs, torch, n_req):
+    """Poisson stream of mixed-size full-Greek-set requests (assets U{1..20},
+    paths U[10k, 400k], steps U{52,126,252,504}) through the serving loop.
+    First the saturated capacity (all requests queued at once), then a
+    Poisson stream at 0.8 of it: p50/p99 latency from submit to result."""
+    free, total = torch.cuda.mem_get_info()
+    pool = int(min(free * 0.7, 160e9))
+    srv = hs.Server(pool, max_slots=4)
+    try:
+        reqs = [r for _, r in W.serving_stream(n_req, 1.0, seed=11)]
+        t0 = time.perf_counter()
+        tickets = [srv.submit(r) for r in reqs]
+        done = {}
+        while len(done) < len(tickets):
+            for t in tickets:
+                if t not in done:
+                    p = srv.poll(t)
+                    if p is not None:
+                        done[t] = p
+            time.sleep(0.001)
+        t_sat = time.perf_counter() - t0
+        steps_sat = sum(hs.num_scenarios(len(r["model"]["S0"]), 31) * r["n_paths"] * r["n_steps"]
+                        for r in reqs)
+        cap = len(reqs) / t_sat
+        rate = 0.8 * cap
+        stream = W.serving_stream(n_req, rate, seed=12)
+        lat = []
+        t0 = time.perf_counter()
+        pending = {}
+        i = 0
+        while i < len(stream) or pending:
+            now = time.perf_counter() - t0
+            while i < len(stream) and stream[i][0] <= now:
+                pending[srv.submit(stream[i][1])] = True
+                i += 1
+            for t in list(pending):
+                p = srv.poll(t)
+                if p is not None:
+                    lat.append(p[1])
+                    del pending[t]
+            time.sleep(0.0005)
+        t_run = time.perf_counter() - t0
+        steps_run = sum(hs.num_scenarios(len(r["model"]["S0"]), 31) * r["n_paths"] * r["n_steps"]
+                        for _, r in stream)
+        st = srv.stats()
+        return {"requests": len(stream), "offered_load": 0.8,
+                "saturated_req_per_s": cap, "saturated_path_steps_per_s": steps_sat / t_sat,
+                "path_steps_per_s": steps_run / t_run,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "pool_GB": pool / 1e9, "pool_peak_GB": st["pool_peak"] / 1e9, "slots": 4}
+    finally:
+        srv.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -69,6 +69,11 @@ def lib(path=None):
         L.orc_price_scenarios.argtypes = [ctypes.c_void_p, dp, dp, ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(ctypes.c_int32)]
         L.orc_price_scenarios.restype = ctypes.c_int
+        L.orc_price_scenarios_replay.argtypes = [ctypes.c_void_p, dp, dp,
+                                                 ctypes.POINTER(ctypes.c_int64),
+                                                 ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int32)]
+        L.orc_price_scenarios_replay.restype = ctypes.c_int
         L.orc_greeks.argtypes = [ctypes.c_int32, ctypes.c_uint32, dp, dp, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, dp, dp, dp, dp, dp, dp, dp]
@@ -228,8 +233,11 @@ def num_scenarios(n_assets, mask):
 
 
 def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed, nthreads=0,
-                 export_tau=False):
-    """The full Greek set: scenario prices, SEs, skipped counts and the Greeks."""
+                 export_tau=False, replay_tau=None):
+    """The full Greek set: scenario prices, SEs, skipped counts and the Greeks.
+
+    replay_tau (scenarios x paths int32): price each scenario with these
+    exercise dates instead of regressing (decision replay)."""
     keep = []
     arrs = [_f64(model[k]) for k in ("S0", "v0", "kappa", "theta", "xi", "rho")]
     C = _f64(corr)
@@ -247,10 +255,15 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed, nthreads=0,
     ses = np.zeros(S)
     skipped = np.zeros(S, dtype=np.int64)
     tau = np.zeros((S, n_paths), dtype=np.int32) if export_tau else None
-    st = lib().orc_price_scenarios(
+    rt = None
+    if replay_tau is not None:
+        rt = np.ascontiguousarray(replay_tau, dtype=np.int32)
+        assert rt.shape == (S, n_paths)
+    st = lib().orc_price_scenarios_replay(
         ctypes.byref(q), _dp(prices), _dp(ses),
         skipped.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-        tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if tau is not None else None)
+        tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if tau is not None else None,
+        rt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if rt is not None else None)
     if st != OK:
         raise ValueError("orc_price_scenarios failed with status %d" % st)
     g = greeks_from_prices(N, mask, arrs[0], arrs[1], bumps, prices)

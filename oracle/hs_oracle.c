@@ -509,9 +509,20 @@ typedef struct {
 } orc_request;
 
 /* Prices of every scenario of the Greek set.  prices/ses/skipped have
- * orc_num_scenarios entries; tau_all (optional) has that many rows of P. */
+ * orc_num_scenarios entries; tau_all (optional) has that many rows of P.
+ * With replay_tau (optional, same shape) each scenario is not regressed but
+ * priced with the given exercise dates (decision replay). */
+int orc_price_scenarios_replay(const orc_request *q, double *prices, double *ses,
+                               int64_t *skipped, int32_t *tau_all, const int32_t *replay_tau);
+
 int orc_price_scenarios(const orc_request *q, double *prices, double *ses, int64_t *skipped,
                         int32_t *tau_all)
+{
+    return orc_price_scenarios_replay(q, prices, ses, skipped, tau_all, NULL);
+}
+
+int orc_price_scenarios_replay(const orc_request *q, double *prices, double *ses,
+                               int64_t *skipped, int32_t *tau_all, const int32_t *replay_tau)
 {
     const int N = q->N;
     if (N < 1 || q->P < 2 || q->n < 1) return ORC_EINVAL;
@@ -571,8 +582,12 @@ int orc_price_scenarios(const orc_request *q, double *prices, double *ses, int64
         if (st != ORC_OK) break;
         double out[2];
         int64_t sk = 0;
-        st = orc_lsmc(feat, q->P, q->n, T, r, q->K, q->cp, q->style, q->m, tbar, q->nthreads, out,
-                      tau_all ? tau_all + s * q->P : NULL, NULL, &sk);
+        if (replay_tau) {
+            st = orc_replay(feat, q->P, q->n, T, r, q->K, q->cp, replay_tau + s * q->P, out);
+        } else {
+            st = orc_lsmc(feat, q->P, q->n, T, r, q->K, q->cp, q->style, q->m, tbar, q->nthreads,
+                          out, tau_all ? tau_all + s * q->P : NULL, NULL, &sk);
+        }
         if (st != ORC_OK) break;
         prices[s] = out[0];
         ses[s] = out[1];

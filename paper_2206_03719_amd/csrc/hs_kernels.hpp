@@ -1,0 +1,33 @@
+// hs_kernels.hpp -- host-side launchers of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "hs_layout.hpp"
+
+namespace hs {
+
+// Path kernel: the asset-count bucket (1,2,3,4,5,6,8,10,12,16,20) that holds N,
+// tasks per wave for a bucket, and the dynamic LDS it needs.
+int paths_nmax_bucket(int N);
+int paths_tmax(bool fp32, int nmax);
+size_t paths_lds_bytes(bool fp32, int nmax);
+hipError_t launch_paths(bool fp32, int nmax, const PathArgs& a, int nchunks, int nblockgroups,
+                        hipStream_t st);
+
+// Gram matrices and their Cholesky factors for dates 1..n-1 of S scenarios.
+hipError_t launch_gram(bool fp32, const LsmcArgs& a, int S, hipStream_t st);
+
+// Backward sweep + price of S scenarios.  q = paths per thread with the state
+// in registers (1,2,4,8,16), or 0 for the state in the workspace.
+int sweep_q_for(int64_t P);
+hipError_t launch_sweep(bool fp32, int q, const LsmcArgs& a, int S, hipStream_t st);
+
+hipError_t launch_philox_words(uint64_t seed, int64_t P, int n, int nb, uint32_t* out,
+                               hipStream_t st);
+hipError_t launch_normals(bool fp32, uint64_t seed, int N, int64_t P, int n, void* eps,
+                          void* eta, hipStream_t st);
+
+}  // namespace hs

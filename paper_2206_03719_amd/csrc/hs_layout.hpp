@@ -1,0 +1,90 @@
+// hs_layout.hpp -- plan tables shared by the host planner and the gfx950
+// kernels: the per-scenario parameters of a Greek set, the "task" list that
+// carries only what differs from the base scenario, and the regression
+// records the Gram kernel hands to the backward sweep.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace hs {
+
+constexpr int kMaxAssets = 20;
+constexpr int kLanes = 64;        // one wave = 64 consecutive paths
+constexpr int kMaxWaves = 8;      // waves per path-kernel block
+constexpr int kOwnPerWave = 4;    // base assets owned by one wave of a block
+constexpr int kGramThreads = 256; // Gram kernel block
+constexpr int kSweepThreads = 1024;
+constexpr int kRegRec = 20;       // doubles per (scenario, date) regression record
+
+// One asset of the base scenario.  rhobar = sqrt(1 - rho^2) (host FP64).
+template <typename R>
+struct AssetP {
+    R S0, v0, kappa, theta, xi, rho, rhobar, pad;
+};
+
+// The base scenario, in the path precision R.
+template <typename R>
+struct BaseP {
+    AssetP<R> a[kMaxAssets];
+    R L[kMaxAssets * kMaxAssets];  // chol(C), row-major, upper part zero
+    R S0_up[kMaxAssets];           // S0_i (1 + h) for the spot-up scenarios
+    R S0_dn[kMaxAssets];           // S0_i (1 - h)
+    R r, dt, invN, pad;
+};
+
+// A task advances one asset of one bumped scenario whose trajectory differs
+// from the base one (v0, T, r or correlation bumps).  Tasks of a scenario
+// are contiguous, in asset order, and cover the scenario's own asset range
+// [lo, hi); assets outside it are the base scenario's, bit for bit.
+template <typename R>
+struct TaskP {
+    int32_t asset, own_row, first, last, scen, lo, hi, pad;
+    R S0, v0, kappa, theta, xi, rho, rhobar, r, dt, pad1;
+    R L[kMaxAssets];  // the scenario's Cholesky row of `asset` (own_row == 1)
+};
+
+// One wave's share of a block: its tasks, and whether it writes the base and
+// spot-bumped scenarios (which need no state of their own).
+struct GroupP {
+    int32_t task0, ntask;
+    int32_t base_scen;  // feature plane of the base scenario, or -1
+    int32_t spot_up0;   // plane of spot-up asset 0 (asset a at +a), or -1
+    int32_t spot_dn0;   // plane of spot-down asset 0, or -1
+    int32_t pad[3];
+};
+
+struct PathArgs {
+    const void* base;      // BaseP<R>
+    const void* tasks;     // TaskP<R>[]
+    const GroupP* groups;  // [n_blockgroups * W]
+    void* feat;            // R2 planes [scen][date][path]
+    int64_t P;
+    int64_t plane;         // elements per scenario plane (dates stored * P)
+    int32_t n, N, W, store_all;
+    uint32_t key0, key1;
+};
+
+// Regression record of one (scenario, date): packed lower Cholesky factor of
+// the Gram matrix (m(m+1)/2 entries), reciprocals of its diagonal, the
+// regression-set means, ok flag and set size.
+struct RegRec {
+    double L[15];
+    double cU, cA, ok, cnt, pad;
+};
+static_assert(sizeof(RegRec) == kRegRec * sizeof(double), "RegRec layout");
+
+struct LsmcArgs {
+    const void* feat;      // R2 planes [scen][date][path]
+    RegRec* reg;           // [scen][date] (date index k-1 for date k)
+    const double* disc;    // [scen][n+1] exp(-r j dt), host libm
+    double* out;           // [scen][4]: price, se, skipped, itm-count
+    double* cf;            // [scen][P] (state in workspace), else null
+    int32_t* tau;          // [scen][P] state / export, or null
+    int64_t P;
+    int64_t plane;
+    int32_t n, m, cp, american;
+    double K, inv_K, inv_tbar;
+    int32_t export_tau, pad;
+};
+
+}  // namespace hs

@@ -1,0 +1,92 @@
+// hs_plan.hpp -- host planner of a Greek set: validation, scenario expansion
+// (bump-and-revalue with common random numbers), the task/group tables of
+// the path kernel, and the workspace layout.  FP64 on the host throughout.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hs_api.h"
+#include "hs_layout.hpp"
+
+namespace hs {
+
+void set_error(const char* fmt, ...);
+
+// A request copied into host-owned storage.
+struct Request {
+    int N = 0;
+    std::vector<double> S0, v0, kappa, theta, xi, rho;
+    double r = 0.0;
+    std::vector<double> C;  // N x N
+    hs_option opt{};
+    int64_t P = 0;
+    int32_t n = 0;
+    hs_bumps bumps{};
+    hs_opts opts{};
+};
+
+hs_status copy_request(const hs_model* model, const double* corr, const hs_option* option,
+                       int64_t n_paths, int32_t n_steps, const hs_bumps* bumps,
+                       const hs_opts* opts, Request& out);
+hs_status validate(const Request& q);  // ranges, symmetry, SPD of every scenario
+
+// One scenario of the Greek set (host FP64).
+struct Scenario {
+    int kind = 0;  // 0 base, 1 spot up, 2 spot down, 3 v0, 4 T, 5 r, 6 corr
+    int i = -1, j = -1;
+    std::vector<double> S0, v0, L;  // L = chol(C_scenario), N x N
+    double r = 0.0, T = 0.0;
+    int lo = 0, hi = 0;  // own asset range (assets whose path differs from base)
+};
+
+int basis_m(const Request& q);
+bool cholesky(int N, const std::vector<double>& C, std::vector<double>& L);
+hs_status expand_scenarios(const Request& q, std::vector<Scenario>& out);
+int64_t num_scenarios(int N, uint32_t mask);
+
+// A pass runs a subset of scenarios whose features fit the workspace at once.
+struct Pass {
+    std::vector<int> scen;  // canonical scenario indices, in plane order
+    bool has_base_spot = false;
+};
+
+// Byte offsets of a pass's regions inside the workspace.
+struct Layout {
+    size_t base = 0, tasks = 0, groups = 0, disc = 0, reg = 0, out = 0, tau = 0, cf = 0,
+           feat = 0, total = 0;
+};
+
+struct Shape {
+    bool fp32 = true;
+    bool american = true;
+    int nmax = 0, tmax = 0;
+    int sweep_q = 0;        // 0 = state in the workspace
+    bool need_tau = false;  // tau region (export or workspace state)
+};
+
+Shape shape_of(const Request& q);
+Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, int n_groups);
+
+// Everything one pass uploads and launches.
+struct PassPlan {
+    std::vector<unsigned char> base;    // BaseP<R>
+    std::vector<unsigned char> tasks;   // TaskP<R>[]
+    std::vector<GroupP> groups;         // [nbg * W]
+    std::vector<double> disc;           // [scen][n+1]
+    int W = 1, nbg = 1, nchunks = 1, ntasks = 0;
+    Layout lay;
+};
+
+PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,
+                   const Pass& pass, int target_waves);
+// Splits the Greek set into passes that each fit `workspace_bytes`
+// (one pass if everything fits).  Empty result = even one unit does not fit.
+std::vector<Pass> make_passes(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,
+                              size_t workspace_bytes, size_t* min_bytes);
+
+// Greeks (host FP64) from scenario prices in canonical order.
+void greeks_from_prices(const Request& q, const std::vector<double>& price, hs_greeks* out);
+
+}  // namespace hs

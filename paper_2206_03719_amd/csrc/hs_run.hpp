@@ -1,0 +1,29 @@
+// hs_run.hpp -- one Greek set on one stream (used by the C ABI and the server).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/hs_api.h"
+#include "hs_plan.hpp"
+
+namespace hs {
+
+struct RunResult {
+    std::vector<double> price, se;
+    std::vector<int64_t> skipped;
+    std::vector<int32_t> tau;  // [scenario][path] when exported
+    double t_paths = 0, t_gram = 0, t_sweep = 0, t_total = 0;
+    int n_passes = 0;
+};
+
+// Enqueues and completes (synchronizes st) the whole Greek set of a validated
+// request in the given workspace; target_waves <= 0 = default.
+hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream_t st,
+                        RunResult& res, int target_waves);
+void fill_greeks(const Request& q, const RunResult& res, hs_greeks* out);
+size_t workspace_bound(const Request& q, bool minimum);
+int default_target_waves();
+
+}  // namespace hs

@@ -1,0 +1,142 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol that
+include/hs_api.h declares, sizes workspaces, and rejects bad input before any
+device work (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2206_03719_amd as hs
+import workloads as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "hs_api.h")
+FAKE_WS = 1 << 40  # never dereferenced: every case below fails validation or sizing first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = hs.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(hs._SIGS)
+
+
+def test_num_scenarios_matches_oracle():
+    for N in (1, 2, 5, 10, 20):
+        for mask in (0, 1, 2, 3, 16, 31):
+            assert hs.num_scenarios(N, mask) == oracle.num_scenarios(N, mask)
+    b = hs.Bumps(31, 0.01, 0.01, 1 / 252, 1e-3, 0.01)
+    assert hs.lib().hs_num_scenarios(0, ctypes.byref(b)) == -1
+    assert hs.lib().hs_num_scenarios(21, ctypes.byref(b)) == -1
+
+
+def test_workspace_sizes():
+    w = W.best_of_call()
+    full = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"])
+    mn = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"], minimum=True)
+    feat = 28 * 252 * 25000 * 8
+    assert feat <= full < feat * 1.02
+    assert mn < full
+    f64 = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"], precision="fp64")
+    assert f64 > 1.9 * feat
+    eu = dict(w["option"], style="european")
+    assert hs.workspace_bytes(w["model"], eu, 25000, 252, w["bumps"]) < full / 100
+
+
+def _call(w, ws_bytes=1 << 34, workspace=FAKE_WS, corr=None, n_paths=None, n_steps=None,
+          **kw):
+    m = hs._Marshal(w["model"], w["corr"] if corr is None else corr, w["option"], w["bumps"],
+                    42, kw.pop("precision", "fp32"), kw.pop("flags", 0), kw.pop("wpb", 0),
+                    kw.pop("sweep_mode", 0))
+    for k, v in kw.items():
+        obj, field = k.split("__")
+        setattr(getattr(m, obj), field, v)
+    g = hs.Greeks()
+    st = hs.lib().hs_price_greeks(ctypes.byref(m.model), m.corr_ptr, ctypes.byref(m.option),
+                                  w["n_paths"] if n_paths is None else n_paths,
+                                  w["n_steps"] if n_steps is None else n_steps,
+                                  ctypes.byref(m.bumps), ctypes.byref(m.opts),
+                                  ctypes.c_void_p(workspace), ws_bytes, None, ctypes.byref(g))
+    return st, hs.lib().hs_last_error().decode()
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(n_paths=1), hs.EINVAL),
+    (dict(n_steps=0), hs.EINVAL),
+    (dict(n_steps=5000), hs.EINVAL),
+    (dict(model__n_assets=21), hs.EINVAL),
+    (dict(option__K=-1.0), hs.EINVAL),
+    (dict(option__T=0.0), hs.EINVAL),
+    (dict(option__cp=7), hs.EINVAL),
+    (dict(option__underlying=0), hs.EINVAL),      # SINGLE with 5 assets
+    (dict(bumps__spot_rel=1.5), hs.EINVAL),
+    (dict(bumps__T_abs=2.0), hs.EINVAL),
+    (dict(bumps__mask=64), hs.EINVAL),
+    (dict(opts__precision=3), hs.EINVAL),
+    (dict(opts__waves_per_block=9), hs.EINVAL),
+    (dict(opts__sweep_mode=1, n_paths=200000), hs.EINVAL),
+    (dict(ws_bytes=4096), hs.ENOMEM),
+])
+def test_invalid_inputs_rejected_before_device_work(case, expect):
+    w = W.best_of_call(n_paths=1000, n_steps=16)
+    st, msg = _call(w, **case)
+    assert st == expect, msg
+    assert msg
+
+
+def test_model_parameter_ranges():
+    base = W.best_of_call(n_paths=1000, n_steps=16)
+    for key, val in [("S0", 0.0), ("v0", -0.01), ("kappa", -1.0), ("theta", 0.0), ("xi", -0.1),
+                     ("rho", 1.0), ("rho", np.nan)]:
+        w = dict(base)
+        w["model"] = {k: (np.array(v, copy=True) if k != "r" else v) for k, v in base["model"].items()}
+        w["model"][key][2] = val
+        st, msg = _call(w)
+        assert st == hs.EINVAL, (key, msg)
+
+
+def test_correlation_checks():
+    w = W.best_of_call(n_paths=1000, n_steps=16)
+    C = w["corr"].copy()
+    C[0, 1] += 0.01  # not symmetric
+    assert _call(w, corr=C)[0] == hs.EINVAL
+    C = w["corr"].copy()
+    C[2, 2] = 0.9
+    assert _call(w, corr=C)[0] == hs.EINVAL
+    C = np.eye(5)
+    C[0, 1] = C[1, 0] = 0.999
+    C[0, 2] = C[2, 0] = 0.999
+    C[1, 2] = C[2, 1] = -0.999
+    assert _call(w, corr=C)[0] == hs.ENOTSPD
+    # SPD, but the +0.01 correlation bump of (0,1) is not
+    C = np.eye(5)
+    C[0, 1] = C[1, 0] = 0.995
+    st, msg = _call(w, corr=C)
+    assert st == hs.ENOTSPD and "(0,1)" in msg
+
+
+def test_vega_needs_positive_v0():
+    w = W.best_of_call(n_paths=1000, n_steps=16)
+    w["model"] = dict(w["model"], v0=np.array([0.04, 0.0, 0.05, 0.03, 0.02]))
+    assert _call(w)[0] == hs.EINVAL
+    w["bumps"] = dict(w["bumps"], mask=31 & ~2)
+    # without vega, v0 = 0 is valid: fails only on the (fake) tiny workspace
+    assert _call(w, ws_bytes=4096)[0] == hs.ENOMEM
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(hs, "_lib", None)
+    monkeypatch.setattr(hs, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        hs.lib()

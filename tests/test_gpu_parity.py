@@ -1,0 +1,260 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs and the same Philox streams.
+
+Bars: bit-exact Philox words; FP64 paths within 1e-13 relative of the oracle's
+features and every FP64 scenario price within 1e-12 relative with identical
+exercise dates; FP32 paths within 1e-4 relative on prices, with the arithmetic
+error isolated by decision replay and the decision flips counted; bit-for-bit
+invariance across launch shapes, sweep modes and workspace passes."""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+hs = None
+
+
+def setup_module(module):
+    global hs
+    import paper_2206_03719_amd as _hs
+    hs = _hs
+    hs.lib()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu(w, precision, **kw):
+    return hs.price_greeks(w["model"], w["corr"], w["option"], w["n_paths"], w["n_steps"],
+                           w["bumps"], seed=w["seed"], precision=precision, **kw)
+
+
+def orc(w, **kw):
+    return oracle.price_greeks(w["model"], w["corr"], w["option"], w["n_paths"], w["n_steps"],
+                               w["bumps"], w["seed"], **kw)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# random numbers
+
+def test_philox_words_bit_exact():
+    _say("philox words: seed 42, 300 paths x 7 steps x 3 blocks")
+    words = hs.philox_words(42, 300, 7, 3)
+    for p in range(300):
+        for k in range(7):
+            for j in range(3):
+                assert list(words[p, k, j]) == oracle.philox([p, k, j, 0], [42, 0]), (p, k, j)
+    words = hs.philox_words((7 << 32) | 99, 50, 2, 2)
+    for p in range(50):
+        for k in range(2):
+            for j in range(2):
+                assert list(words[p, k, j]) == oracle.philox([p, k, j, 0], [99, 7])
+
+
+@pytest.mark.parametrize("N", [1, 5, 20])
+def test_normals(N):
+    _say("normals N=%d" % N)
+    P, n = 200, 5
+    e64, h64 = hs.normals(42, N, P, n, "fp64")
+    e32, h32 = hs.normals(42, N, P, n, "fp32")
+    for p in range(P):
+        for k in range(n):
+            re, rh = oracle.normals(N, 42, p, k)
+            assert np.abs(e64[p, k] - re).max() <= 4e-15
+            assert np.abs(h64[p, k] - rh).max() <= 4e-15
+            assert np.abs(e32[p, k] - re).max() <= 2e-6
+            assert np.abs(h32[p, k] - rh).max() <= 2e-6
+
+
+# ---------------------------------------------------------------------------
+# paths + path reduction (the paper's measured kernel)
+
+@pytest.mark.parametrize("N", [1, 3, 5, 12, 20])
+def test_path_features_fp64(N):
+    _say("path features fp64 N=%d" % N)
+    w = W.best_of_call(n_assets=N, n_paths=1000, n_steps=40)
+    ref = oracle.features(w["model"], w["corr"], 1.0, 40, 1000, 42)
+    got = hs.path_features(w["model"], w["corr"], 1.0, 1000, 40, seed=42,
+                           precision="fp64").cpu().numpy()
+    assert got.shape == ref.shape
+    assert rel(got[..., 0], ref[..., 0]).max() <= 1e-13
+    assert np.abs(got[..., 1] - ref[..., 1]).max() <= 1e-15 + 1e-13 * np.abs(ref[..., 1]).max()
+
+
+@pytest.mark.parametrize("N", [1, 5, 10])
+def test_path_features_fp32(N):
+    _say("path features fp32 N=%d" % N)
+    w = W.best_of_call(n_assets=N, n_paths=777, n_steps=252)
+    ref = oracle.features(w["model"], w["corr"], 1.0, 252, 777, 42)
+    got = hs.path_features(w["model"], w["corr"], 1.0, 777, 252, seed=42,
+                           precision="fp32").cpu().numpy().astype(np.float64)
+    assert rel(got[..., 0], ref[..., 0]).max() <= 5e-5
+    assert np.abs(got[..., 1] - ref[..., 1]).max() <= 5e-6
+
+
+# ---------------------------------------------------------------------------
+# Greek sets, FP64: the oracle's numbers to 1e-12
+
+def _fp64_parity(w, **kw):
+    g = gpu(w, "fp64", export_tau=True, **kw)
+    o = orc(w, export_tau=True)
+    worst = rel(g["scenario_price"], o["scenario_price"]).max()
+    flips = int((g["tau"] != o["tau"]).sum())
+    _say("  fp64 worst scenario rel err %.3e, tau mismatches %d" % (worst, flips))
+    assert flips == 0
+    assert worst <= 1e-12
+    assert np.allclose(g["scenario_se"], o["scenario_se"], rtol=1e-9, atol=0)
+    assert g["skipped_regressions"] == int(o["skipped"].sum())
+    # each Greek against the bound propagated from 1e-12 on every scenario price
+    V = np.abs(o["scenario_price"])
+    N = len(w["model"]["S0"])
+    if w["bumps"]["mask"] & 1:
+        hsv = w["bumps"]["spot_rel"] * np.asarray(w["model"]["S0"])
+        for a in range(N):
+            up, dn = V[1 + a], V[1 + N + a]
+            assert abs(g["delta"][a] - o["delta"][a]) <= 4e-12 * (up + dn) / (2 * hsv[a])
+            assert abs(g["gamma"][a] - o["gamma"][a]) <= 4e-12 * (up + 2 * V[0] + dn) / hsv[a] ** 2
+    return g, o
+
+
+def test_single_asset_put_fp64():
+    _say("single-asset Heston American put, 1024 x 64, fp64")
+    w = W.single_asset_put()
+    g, o = _fp64_parity(w)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "single_asset_put_oracle.json")))
+    assert np.allclose(g["scenario_price"], gold["scenario_price"], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("N,P,n,style,basis", [
+    (5, 3000, 50, "american", "auto"),
+    (3, 777, 30, "american", "quad"),
+    (10, 1500, 20, "american", "auto"),
+    (4, 2000, 25, "european", "auto"),
+    (1, 1000, 12, "american", "auto"),
+])
+def test_greek_set_fp64(N, P, n, style, basis):
+    _say("greek set fp64 N=%d P=%d n=%d %s %s" % (N, P, n, style, basis))
+    w = W.best_of_call(n_assets=N, n_paths=P, n_steps=n)
+    w["option"]["style"] = style
+    w["option"]["basis"] = basis
+    _fp64_parity(w)
+
+
+def test_put_on_max_fp64():
+    _say("american put on the max of 3, fp64")
+    w = W.best_of_call(n_assets=3, n_paths=2000, n_steps=30)
+    w["option"]["cp"] = "put"
+    w["option"]["K"] = 125.0
+    _fp64_parity(w)
+
+
+# ---------------------------------------------------------------------------
+# Greek sets, FP32 paths (FP64 regression): 1e-4 on prices, decisions replayed
+
+def _fp32_parity(w):
+    g = gpu(w, "fp32", export_tau=True)
+    o = orc(w, export_tau=True)
+    rep = orc(w, replay_tau=g["tau"])  # FP64 prices of the GPU's own decisions
+    price_err = rel(g["scenario_price"], o["scenario_price"])
+    arith_err = rel(g["scenario_price"], rep["scenario_price"])
+    flips = (g["tau"] != o["tau"]).sum(axis=1)
+    report = {"workload": w["name"], "max_price_rel_err": float(price_err.max()),
+              "max_arith_rel_err": float(arith_err.max()),
+              "flip_fraction": float(flips.sum() / g["tau"].size)}
+    for key in ("delta", "gamma", "vega", "corr"):
+        if len(o[key]):
+            report["max_%s_rel_err" % key] = float(rel(g[key], o[key]).max())
+    for key in ("theta", "rho"):
+        report["%s_rel_err" % key] = float(rel(g[key], o[key]))
+    _say("  fp32 " + json.dumps(report))
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "fp32_parity_%s.json" % w["name"]), "w") as f:
+        json.dump(report, f, indent=1)
+    assert price_err.max() <= 1e-4
+    assert arith_err.max() <= 1e-5
+    assert rel(g["delta"], o["delta"]).max() <= 1e-3
+    return g, o, report
+
+
+def test_greek_set_fp32_small():
+    _say("greek set fp32 N=5 P=4000 n=64")
+    _fp32_parity(W.best_of_call(n_assets=5, n_paths=4000, n_steps=64))
+
+
+def test_greek_set_fp32_bestof5_full_size():
+    # the 5-asset best-of workload at its full size, in the launch shape the
+    # benchmark times (the oracle runs the same 25k paths: the regression
+    # couples every path)
+    _say("greek set fp32 N=5 P=25000 n=252 (full size)")
+    _fp32_parity(W.best_of_call(n_assets=5, n_paths=25000, n_steps=252))
+
+
+# ---------------------------------------------------------------------------
+# invariances: results are a function of the request alone
+
+def test_bitwise_invariance_launch_shape_and_passes():
+    _say("bitwise invariance: waves per block, sweep mode, workspace passes")
+    w = W.best_of_call(n_assets=5, n_paths=3000, n_steps=40)
+    ref = gpu(w, "fp32")
+    for kw in (dict(waves_per_block=1), dict(waves_per_block=8), dict(sweep_mode=2)):
+        g = gpu(w, "fp32", **kw)
+        assert np.array_equal(g["scenario_price"], ref["scenario_price"]), kw
+        assert np.array_equal(g["scenario_se"], ref["scenario_se"]), kw
+    import torch
+    mn = hs.workspace_bytes(w["model"], w["option"], 3000, 40, w["bumps"], minimum=True)
+    ws = torch.empty(mn, dtype=torch.uint8, device="cuda")
+    g = gpu(w, "fp32", workspace=ws)
+    assert np.array_equal(g["scenario_price"], ref["scenario_price"])
+
+
+@pytest.mark.parametrize("P", [16384, 16385, 25000])
+def test_sweep_modes_across_register_limit(P):
+    # register-resident cash flows up to 16 paths per thread, workspace-resident
+    # beyond; both must price like the oracle and identically to each other
+    _say("sweep modes at P=%d" % P)
+    w = W.best_of_call(n_assets=5, n_paths=P, n_steps=40, mask=0)
+    o = orc(w)
+    a = gpu(w, "fp64", sweep_mode=2)
+    assert rel(a["price"], o["price"]) <= 1e-12
+    if P <= 16384:
+        b = gpu(w, "fp64", sweep_mode=1)
+        assert a["price"] == b["price"] and a["price_se"] == b["price_se"]
+
+
+def test_repeat_runs_identical():
+    w = W.best_of_call(n_assets=4, n_paths=5000, n_steps=30)
+    a = gpu(w, "fp32")
+    b = gpu(w, "fp32")
+    assert np.array_equal(a["scenario_price"], b["scenario_price"])
+
+
+def test_all_out_of_the_money_gpu():
+    w = W.single_asset_put(n_paths=512, n_steps=16)
+    w["option"]["K"] = 1.0
+    g = gpu(w, "fp64")
+    assert g["price"] == 0.0 and g["price_se"] == 0.0
+    assert g["skipped_regressions"] == 3 * 15
+
+
+def test_timing_fields():
+    w = W.best_of_call(n_assets=5, n_paths=4096, n_steps=32)
+    g = gpu(w, "fp32", timing=True)
+    assert g["t_paths_ms"] > 0 and g["t_sweep_ms"] > 0
+    assert abs(g["t_total_ms"] - g["t_paths_ms"] - g["t_gram_ms"] - g["t_sweep_ms"]) < 1e-6
