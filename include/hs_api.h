@@ -129,7 +129,11 @@ typedef struct hs_opts {
                                 of 64 paths' scenario groups per block             */
     uint64_t seed;           /* Philox key                                         */
     uint32_t flags;          /* HS_FLAG_*                                          */
-    int32_t sweep_mode;      /* 0 = automatic, 1 = state in registers, 2 = state in workspace */
+    int32_t sweep_mode;      /* backward sweep: 0 = automatic (cluster when it fits the
+                                device), 1 = one workgroup per scenario with the state in
+                                registers (n_paths <= 16384), 2 = one workgroup per scenario
+                                with the state in the workspace, 3 = cluster of workgroups per
+                                scenario (HS_EDEVICE if it cannot be co-resident)          */
     int32_t reserved[4];     /* must be zero                                       */
 } hs_opts;
 

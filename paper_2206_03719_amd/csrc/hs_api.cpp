@@ -2,8 +2,10 @@
 // the path, Gram and sweep kernels on the caller's stream, and the Greeks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -27,6 +29,19 @@ bool hip_ok(hipError_t e, const char* what)
     do {                                     \
         if (!hip_ok((call), (what))) return HS_EDEVICE; \
     } while (0)
+
+// Cluster sweeps wait on each other's workgroups, so two of them must never
+// compete for residency: one cluster launch sequence at a time per process.
+std::mutex g_cluster_mu;
+
+int64_t wall_clock_ticks(double seconds)
+{
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;  // 100 MHz
+    return static_cast<int64_t>(seconds * 1e3 * khz);
+}
 
 double mean_theta(const Request& q)
 {
@@ -124,8 +139,8 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         la.reg = reinterpret_cast<RegRec*>(ws + pp.lay.reg);
         la.disc = reinterpret_cast<const double*>(ws + pp.lay.disc);
         la.out = reinterpret_cast<double*>(ws + pp.lay.out);
-        la.cf = sh.sweep_q == 0 ? reinterpret_cast<double*>(ws + pp.lay.cf) : nullptr;
-        la.tau = sh.need_tau ? reinterpret_cast<int32_t*>(ws + pp.lay.tau) : nullptr;
+        la.cf = reinterpret_cast<double*>(ws + pp.lay.cf);
+        la.tau = reinterpret_cast<int32_t*>(ws + pp.lay.tau);
         la.P = q.P;
         la.plane = pa.plane;
         la.n = q.n;
@@ -142,12 +157,54 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         if (timing) HS_HIP(hipEventRecord(ev[1], st), "hipEventRecord");
         if (sh.american) HS_HIP(launch_gram(sh.fp32, la, Sp, st), "Gram kernel launch");
         if (timing) HS_HIP(hipEventRecord(ev[2], st), "hipEventRecord");
-        HS_HIP(launch_sweep(sh.fp32, sh.sweep_q, la, Sp, st), "sweep kernel launch");
+        // backward sweep: a cluster of workgroups per scenario when it fits the
+        // device, else one workgroup per scenario with the state in the workspace
+        std::unique_lock<std::mutex> cluster_lock(g_cluster_mu, std::defer_lock);
+        uint32_t* sync = reinterpret_cast<uint32_t*>(ws + pp.lay.sync);
+        int32_t* err_flag = reinterpret_cast<int32_t*>(sync);
+        bool cluster = sh.sweep == kSweepCluster;
+        int cap = 0;
+        if (cluster) {
+            cap = cluster_capacity(sh.fp32, sh.cluster_q, cluster_lds_bytes(q.n, sh.cluster_g));
+            if (cap < sh.cluster_g) {
+                if (q.opts.sweep_mode == 3) {
+                    set_error("cluster sweep needs %d co-resident workgroups, the device holds %d",
+                              sh.cluster_g, cap);
+                    return HS_EDEVICE;
+                }
+                cluster = false;
+            }
+        }
+        HS_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(sync), 1, 0, st), "clear sweep status");
+        if (cluster) {
+            HS_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ws + pp.lay.part),
+                                   static_cast<int64_t>(Sp) * (q.n + 2) * sh.cluster_g * kPartStride,
+                                   kEmptySlot, st), "clear partial slots");
+            ClusterArgs ca{};
+            ca.partials = reinterpret_cast<double*>(ws + pp.lay.part);
+            ca.error = err_flag;
+            ca.G = sh.cluster_g;
+            ca.timeout_ticks = wall_clock_ticks(10.0);
+            const int per_launch = std::max(1, cap / sh.cluster_g);
+            cluster_lock.lock();
+            for (int s0 = 0; s0 < Sp; s0 += per_launch) {
+                ca.s0 = s0;
+                HS_HIP(launch_sweep_cluster(sh.fp32, sh.cluster_q, la, ca,
+                                            std::min(per_launch, Sp - s0), st),
+                       "cluster sweep launch");
+            }
+        } else {
+            const int qreg = sh.sweep == kSweepBlockRegs ? sh.sweep_q : 0;
+            HS_HIP(launch_sweep(sh.fp32, qreg, la, Sp, st), "sweep kernel launch");
+        }
         if (timing) HS_HIP(hipEventRecord(ev[3], st), "hipEventRecord");
 
         std::vector<double> out(static_cast<size_t>(Sp) * 4);
+        int32_t err_host = 0;
         HS_HIP(hipMemcpyAsync(out.data(), la.out, out.size() * sizeof(double),
                               hipMemcpyDeviceToHost, st), "download results");
+        HS_HIP(hipMemcpyAsync(&err_host, err_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+               "download sweep status");
         std::vector<int32_t> tau;
         if (la.export_tau) {
             tau.resize(static_cast<size_t>(Sp) * q.P);
@@ -155,6 +212,11 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
                                   hipMemcpyDeviceToHost, st), "download tau");
         }
         HS_HIP(hipStreamSynchronize(st), "stream synchronize");
+        if (cluster_lock.owns_lock()) cluster_lock.unlock();
+        if (err_host != 0) {
+            set_error("cluster sweep: a workgroup barrier timed out (device oversubscribed?)");
+            return HS_EDEVICE;
+        }
         for (int i = 0; i < Sp; ++i) {
             const int s = pass.scen[i];
             res.price[s] = out[i * 4 + 0];

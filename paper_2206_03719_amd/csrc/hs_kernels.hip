@@ -23,6 +23,7 @@
 // every result is a deterministic function of the request.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -103,6 +104,18 @@ struct alignas(2 * sizeof(R)) R2 {
     R u, a;
 };
 
+// Read-only parameter tables are read through the constant address space:
+// their loads are uniform across a wave and become scalar (SMEM) loads even
+// though the kernels store to other global buffers.
+template <typename T>
+using cptr = const T __attribute__((address_space(4)))*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const void* p)
+{
+    return reinterpret_cast<cptr<T>>(reinterpret_cast<uintptr_t>(p));
+}
+
 // Uniform (wave-wide) select of arr[i] as a chain of selects with constant
 // indices (instantiated per index, so the array stays in registers).
 template <int J, typename R, int NM>
@@ -142,11 +155,12 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
     const int64_t p = static_cast<int64_t>(blockIdx.x) * kLanes + lane;
     const bool live = p < A.P;
 
-    const BaseP<R>* __restrict__ bp = static_cast<const BaseP<R>*>(A.base);
+    const cptr<BaseP<R>> bp = as_const<BaseP<R>>(A.base);
     const int gidx = static_cast<int>(blockIdx.y) * W + w;
-    const GroupP grp = A.groups[gidx];
-    const TaskP<R>* __restrict__ tk = static_cast<const TaskP<R>*>(A.tasks) + grp.task0;
-    const int ntask = grp.ntask;
+    const cptr<GroupP> gp = as_const<GroupP>(A.groups) + gidx;
+    const int g_task0 = gp->task0, ntask = gp->ntask, g_base = gp->base_scen,
+              g_up0 = gp->spot_up0, g_dn0 = gp->spot_dn0;
+    const cptr<TaskP<R>> tk = as_const<TaskP<R>>(A.tasks) + g_task0;
 
     const R dt = bp->dt;
     const R r = bp->r;
@@ -204,12 +218,12 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
             if (a < N) {
                 R z = R(0);
                 for (int b = 0; b <= a; ++b) z += bp->L[a * kMaxAssets + b] * s_eps[b * kLanes + lane];
-                const AssetP<R> q = bp->a[a];
-                const R zv = q.rho * z + q.rhobar * s_eta[a * kLanes + lane];
+                const cptr<AssetP<R>> q = bp->a + a;
+                const R zv = q->rho * z + q->rhobar * s_eta[a * kLanes + lane];
                 const R vp = Vo[i] > R(0) ? Vo[i] : R(0);
                 const R sq = sqrt_r(vp * dt);
                 Xo[i] = Xo[i] + (r - half * vp) * dt + sq * z;
-                Vo[i] = Vo[i] + q.kappa * (q.theta - vp) * dt + q.xi * sq * zv;
+                Vo[i] = Vo[i] + q->kappa * (q->theta - vp) * dt + q->xi * sq * zv;
                 s_zs[a * kLanes + lane] = z;
                 s_e[a * kLanes + lane] = exp_r(Xo[i]);
                 s_vp[a * kLanes + lane] = Vo[i] > R(0) ? Vo[i] : R(0);
@@ -252,13 +266,13 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
         const R bA = bsum * invN;
 
         if (store && live) {
-            if (grp.base_scen >= 0) {
+            if (g_base >= 0) {
                 R2<R> f;
                 f.u = sm[0];
                 f.a = bA;
-                feat[grp.base_scen * A.plane + off] = f;
+                feat[g_base * A.plane + off] = f;
             }
-            if (grp.spot_up0 >= 0) {
+            if (g_up0 >= 0) {
 #pragma unroll
                 for (int a = 0; a < NMAX; ++a) {
                     if (a < N) {
@@ -270,9 +284,9 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                         R2<R> f;
                         f.a = bA;
                         f.u = su > ex ? su : ex;
-                        feat[(grp.spot_up0 + a) * A.plane + off] = f;
+                        feat[(g_up0 + a) * A.plane + off] = f;
                         f.u = sd > ex ? sd : ex;
-                        feat[(grp.spot_dn0 + a) * A.plane + off] = f;
+                        feat[(g_dn0 + a) * A.plane + off] = f;
                     }
                 }
             }
@@ -283,40 +297,40 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 #pragma unroll
         for (int t = 0; t < TMAX; ++t) {
             if (t < ntask) {
-                const TaskP<R>& T = tk[t];
-                const int a = T.asset;
+                const cptr<TaskP<R>> T = tk + t;
+                const int a = T->asset;
                 R z;
-                if (T.own_row) {
+                if (T->own_row) {
                     z = R(0);
 #pragma unroll
-                    for (int b = 0; b < NMAX; ++b) z += T.L[b] * eps[b];
+                    for (int b = 0; b < NMAX; ++b) z += T->L[b] * eps[b];
                 } else {
                     z = s_zs[a * kLanes + lane];
                 }
-                const R zv = T.rho * z + T.rhobar * s_eta[a * kLanes + lane];
+                const R zv = T->rho * z + T->rhobar * s_eta[a * kLanes + lane];
                 const R vp = tV[t] > R(0) ? tV[t] : R(0);
-                const R sq = sqrt_r(vp * T.dt);
-                tX[t] = tX[t] + (T.r - half * vp) * T.dt + sq * z;
-                tV[t] = tV[t] + T.kappa * (T.theta - vp) * T.dt + T.xi * sq * zv;
-                const R S = T.S0 * exp_r(tX[t]);
+                const R sq = sqrt_r(vp * T->dt);
+                tX[t] = tX[t] + (T->r - half * vp) * T->dt + sq * z;
+                tV[t] = tV[t] + T->kappa * (T->theta - vp) * T->dt + T->xi * sq * zv;
+                const R S = T->S0 * exp_r(tX[t]);
                 const R vpt = tV[t] > R(0) ? tV[t] : R(0);
-                if (T.first) {
-                    runM = T.lo > 0 ? pick(pm, T.lo - 1) : R(0);
-                    runS = T.lo > 0 ? pick(ps, T.lo - 1) : R(0);
+                if (T->first) {
+                    runM = T->lo > 0 ? pick(pm, T->lo - 1) : R(0);
+                    runS = T->lo > 0 ? pick(ps, T->lo - 1) : R(0);
                 }
                 runM = S > runM ? S : runM;
                 runS = runS + vpt;
-                if (T.last) {
-                    if (T.hi < N) {
-                        const R tail = pick(sm, T.hi);
+                if (T->last) {
+                    if (T->hi < N) {
+                        const R tail = pick(sm, T->hi);
                         runM = tail > runM ? tail : runM;
-                        runS = runS + (bsum - pick(ps, T.hi - 1));
+                        runS = runS + (bsum - pick(ps, T->hi - 1));
                     }
                     if (store && live) {
                         R2<R> f;
                         f.u = runM;
                         f.a = runS * invN;
-                        feat[T.scen * A.plane + off] = f;
+                        feat[T->scen * A.plane + off] = f;
                     }
                 }
             }
@@ -371,27 +385,76 @@ __device__ __forceinline__ void basis(int m, double U, double Av, double cU, dou
     phi[4] = x * wv;
 }
 
+// Packed row-major lower Cholesky of the Gram matrix into the record; a pivot
+// at or below 1e-12 of its diagonal entry marks the date as skipped.
+__device__ __forceinline__ void gram_finish(int m, const double (&g)[15], double cU, double cA,
+                                            double cnt, RegRec* rr)
+{
+    double L[15];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) L[i] = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            if (i < m) {
+                double acc = g[i * (i + 1) / 2 + j];
+#pragma unroll
+                for (int q = 0; q < j; ++q) acc -= L[i * (i + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+                if (i == j) {
+                    ok = ok && acc > 1e-12 * g[i * (i + 1) / 2 + i];
+                    L[i * (i + 1) / 2 + i] = ok ? sqrt(acc) : 1.0;
+                } else {
+                    L[i * (i + 1) / 2 + j] = acc / L[j * (j + 1) / 2 + j];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 15; ++i) rr->L[i] = ok ? L[i] : 0.0;
+    rr->cU = cU;
+    rr->cA = cA;
+    rr->ok = ok ? 1.0 : 0.0;
+    rr->cnt = cnt;
+}
+
 // ---------------------------------------------------------------------------
 // Gram kernel: block (date k = blockIdx.x + 1, scenario blockIdx.y).
 
 template <typename R>
 __global__ void __launch_bounds__(kGramThreads) k_gram(const LsmcArgs A)
 {
+    constexpr int U1 = 8, U2 = 4;  // loads in flight per thread in the two passes
     __shared__ double red[(kGramThreads / 64) * 15];
     const int s = blockIdx.y;
     const int k = blockIdx.x + 1;
     const R2<R>* __restrict__ F =
         static_cast<const R2<R>*>(A.feat) + s * A.plane + static_cast<int64_t>(k - 1) * A.P;
     const int nw = kGramThreads / 64;
+    const int64_t P = A.P;
 
     double c3[3] = {0.0, 0.0, 0.0};
-    for (int64_t p = threadIdx.x; p < A.P; p += kGramThreads) {
-        const R2<R> f = F[p];
-        const double U = static_cast<double>(f.u);
-        if (payoff(A.cp, A.K, U) > 0.0) {
-            c3[0] += 1.0;
-            c3[1] += U;
-            c3[2] += static_cast<double>(f.a);
+    for (int64_t p0 = threadIdx.x; p0 < P; p0 += kGramThreads * U1) {
+        R2<R> f[U1];
+#pragma unroll
+        for (int u = 0; u < U1; ++u) {
+            const int64_t p = p0 + u * kGramThreads;
+            if (p < P) {
+                f[u] = F[p];
+            } else {
+                f[u].u = R(0);
+                f[u].a = R(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U1; ++u) {
+            const double U = static_cast<double>(f[u].u);
+            if (p0 + u * kGramThreads < P && payoff(A.cp, A.K, U) > 0.0) {
+                c3[0] += 1.0;
+                c3[1] += U;
+                c3[2] += static_cast<double>(f[u].a);
+            }
         }
     }
     block_sum<3>(c3, red, nw);
@@ -410,47 +473,34 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const LsmcArgs A)
     double g[15];
 #pragma unroll
     for (int i = 0; i < 15; ++i) g[i] = 0.0;
-    for (int64_t p = threadIdx.x; p < A.P; p += kGramThreads) {
-        const R2<R> f = F[p];
-        const double U = static_cast<double>(f.u);
-        if (payoff(A.cp, A.K, U) > 0.0) {
-            double phi[5];
-            basis(m, U, static_cast<double>(f.a), cU, cA, A.inv_K, A.inv_tbar, phi);
-            int idx = 0;
+    for (int64_t p0 = threadIdx.x; p0 < P; p0 += kGramThreads * U2) {
+        R2<R> f[U2];
 #pragma unroll
-            for (int i = 0; i < 5; ++i)
+        for (int u = 0; u < U2; ++u) {
+            const int64_t p = p0 + u * kGramThreads;
+            if (p < P) {
+                f[u] = F[p];
+            } else {
+                f[u].u = R(0);
+                f[u].a = R(0);
+            }
+        }
 #pragma unroll
-                for (int j = 0; j <= i; ++j, ++idx)
-                    if (i < m) g[idx] += phi[i] * phi[j];
+        for (int u = 0; u < U2; ++u) {
+            const double U = static_cast<double>(f[u].u);
+            if (p0 + u * kGramThreads < P && payoff(A.cp, A.K, U) > 0.0) {
+                double phi[5];
+                basis(m, U, static_cast<double>(f[u].a), cU, cA, A.inv_K, A.inv_tbar, phi);
+                int idx = 0;
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int b = 0; b <= a; ++b, ++idx) g[idx] += phi[a] * phi[b];
+            }
         }
     }
     block_sum<15>(g, red, nw);
-    if (threadIdx.x == 0) {
-        // packed row-major lower Cholesky; a pivot at or below 1e-12 of its
-        // diagonal entry marks the date as skipped
-        double L[15];
-        bool ok = true;
-        for (int i = 0; i < m && ok; ++i) {
-            for (int j = 0; j <= i; ++j) {
-                double acc = g[i * (i + 1) / 2 + j];
-                for (int q = 0; q < j; ++q) acc -= L[i * (i + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
-                if (i == j) {
-                    if (!(acc > 1e-12 * g[i * (i + 1) / 2 + i])) {
-                        ok = false;
-                        break;
-                    }
-                    L[i * (i + 1) / 2 + i] = sqrt(acc);
-                } else {
-                    L[i * (i + 1) / 2 + j] = acc / L[j * (j + 1) / 2 + j];
-                }
-            }
-        }
-        for (int i = 0; i < 15; ++i) rr->L[i] = ok ? L[i] : 0.0;
-        rr->cU = cU;
-        rr->cA = cA;
-        rr->ok = ok ? 1.0 : 0.0;
-        rr->cnt = cnt;
-    }
+    if (threadIdx.x == 0) gram_finish(m, g, cU, cA, cnt, rr);
 }
 
 // ---------------------------------------------------------------------------
@@ -648,6 +698,280 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// Cluster sweep: G workgroups per scenario, each holding 256 Q paths' cash
+// flow, exercise date and two dates of features in registers.  Once per
+// exercise date the workgroups of a scenario exchange their right-hand-side
+// partials through per-date slots in the workspace: each slot starts empty
+// (kEmptySlot) and receives exactly one 64-bit value, so a reader that sees a
+// non-empty slot has the value itself -- no counter, no fence.  Every
+// workgroup folds the G partials in workgroup order (the same sum everywhere)
+// and solves for the regression coefficients itself.  A wait longer than
+// timeout_ticks of the wall clock sets the error flag and all workgroups
+// leave the kernel.
+
+// v: this workgroup's reduced partial (same in every thread).  On return v
+// holds the scenario total; false if a wait timed out.
+template <int K>
+__device__ __forceinline__ bool cluster_sum(double (&v)[K], int m, double* row, int G, int g,
+                                            const ClusterArgs& C, double* gat, int* flag)
+{
+    if (G == 1) return true;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if (q < m)
+                __hip_atomic_store(reinterpret_cast<uint64_t*>(row + g * kPartStride + q),
+                                   __builtin_bit_cast(uint64_t, v[q]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int i = threadIdx.x; i < G * m; i += kClusterThreads) {
+        const int gg = i / m, q = i - gg * m;
+        uint64_t* slot = reinterpret_cast<uint64_t*>(row + gg * kPartStride + q);
+        uint64_t x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (x == kEmptySlot) {
+            const long long t0 = wall_clock64();
+            for (;;) {
+                __builtin_amdgcn_s_sleep(2);
+                x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (x != kEmptySlot) break;
+                if (__hip_atomic_load(C.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                    wall_clock64() - t0 > C.timeout_ticks) {
+                    __hip_atomic_store(C.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    *flag = 0;
+                    break;
+                }
+            }
+        }
+        gat[gg * K + q] = __builtin_bit_cast(double, x);
+    }
+    __syncthreads();
+    if (*flag == 0) return false;
+    if (threadIdx.x < m) {
+        double acc = gat[threadIdx.x];
+        for (int gg = 1; gg < G; ++gg) acc += gat[gg * K + threadIdx.x];
+        gat[G * K + threadIdx.x] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = q < m ? gat[G * K + q] : 0.0;
+    __syncthreads();
+    return true;
+}
+
+template <typename R, int Q>
+__global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArgs A,
+                                                                   const ClusterArgs C)
+{
+    extern __shared__ unsigned char hs_smem[];
+    constexpr int NW = kClusterThreads / 64;
+    const int n = A.n;
+    const int G = C.G;
+    double* const sdisc = reinterpret_cast<double*>(hs_smem);  // [n+1]
+    double* const red = sdisc + ((n + 2) & ~1);                 // [NW][5]
+    double* const gat = red + NW * 5;                           // [G+1][5]
+    int* const flag = reinterpret_cast<int*>(gat + (G + 1) * 5);
+    const int sl = blockIdx.x / G;
+    const int g = blockIdx.x - sl * G;
+    const int s = C.s0 + sl;
+    const int64_t P = A.P;
+    const int m = A.m;
+    const R2<R>* __restrict__ F = static_cast<const R2<R>*>(A.feat) + s * A.plane;
+    for (int j = threadIdx.x; j <= n; j += kClusterThreads)
+        sdisc[j] = A.disc[static_cast<int64_t>(s) * (n + 1) + j];
+    if (threadIdx.x == 0) *flag = 1;
+    __syncthreads();
+
+    double* const part = C.partials + static_cast<int64_t>(s) * (n + 2) * G * kPartStride;
+    const cptr<RegRec> recs = as_const<RegRec>(A.reg) + static_cast<int64_t>(s) * n;
+    const int64_t pbase = static_cast<int64_t>(g) * (kClusterThreads * Q) + threadIdx.x;
+    const int64_t last = A.american ? static_cast<int64_t>(n - 1) * P : 0;
+
+    double cf[Q];
+    int tau[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t p = pbase + i * kClusterThreads;
+        cf[i] = p < P ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) : 0.0;
+        tau[i] = n;
+    }
+
+    double beta[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double bcU = 0.0, bcA = 0.0;
+    bool have = false;  // beta of the later date k+1 is valid
+    double skipped = 0.0;
+    // cu/ca: features of date k (this iteration's regression); pu/pa: features
+    // of date k+1 for its exercise decision, then the prefetch of date k-1
+    R cu[Q], ca[Q], pu[Q], pa[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        pu[i] = R(0);
+        pa[i] = R(0);
+        cu[i] = R(0);
+        ca[i] = R(0);
+    }
+    if (A.american && n >= 2) {
+        const R2<R>* __restrict__ F0 = F + static_cast<int64_t>(n - 2) * P;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t p = pbase + i * kClusterThreads;
+            if (p < P) {
+                const R2<R> f = F0[p];
+                cu[i] = f.u;
+                ca[i] = f.a;
+            }
+        }
+    }
+    if (A.american) {
+        // regression record of date k, loaded one date ahead
+        double r_ok = n >= 2 ? recs[n - 2].ok : 0.0;
+        double r_cU = n >= 2 ? recs[n - 2].cU : 0.0;
+        double r_cA = n >= 2 ? recs[n - 2].cA : 0.0;
+        for (int k = n - 1; k >= 1; --k) {
+            const bool ok = r_ok != 0.0;
+            const double cU = r_cU, cA = r_cA;
+            if (k > 1) {
+                r_ok = recs[k - 2].ok;
+                r_cU = recs[k - 2].cU;
+                r_cA = recs[k - 2].cA;
+            }
+            // exercise at date k+1 with its regression
+            if (have) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const double U = static_cast<double>(pu[i]);
+                    const double h = payoff(A.cp, A.K, U);
+                    if (pbase + i * kClusterThreads < P && h > 0.0) {
+                        double phi[5];
+                        basis(m, U, static_cast<double>(pa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
+                        double cont = 0.0;
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) cont += phi[q] * beta[q];
+                        if (h > cont) {
+                            cf[i] = h;
+                            tau[i] = k + 1;
+                        }
+                    }
+                }
+            }
+            const cptr<RegRec> rr = recs + (k - 1);
+            double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (ok) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const double U = static_cast<double>(cu[i]);
+                    if (pbase + i * kClusterThreads < P && payoff(A.cp, A.K, U) > 0.0) {
+                        double phi[5];
+                        basis(m, U, static_cast<double>(ca[i]), cU, cA, A.inv_K, A.inv_tbar, phi);
+                        const double Y = cf[i] * sdisc[tau[i] - k];
+#pragma unroll
+                        for (int q = 0; q < 5; ++q)
+                            if (q < m) b[q] += phi[q] * Y;
+                    }
+                }
+                block_sum<5>(b, red, NW);
+            }
+            // prefetch date k-1 while the scenario's workgroups meet
+            if (k > 1) {
+                const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 2) * P;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const int64_t p = pbase + i * kClusterThreads;
+                    if (p < P) {
+                        const R2<R> f = Fn[p];
+                        pu[i] = f.u;
+                        pa[i] = f.a;
+                    }
+                }
+            }
+            if (ok) {
+                if (!cluster_sum<5>(b, m, part + static_cast<int64_t>(k) * G * kPartStride, G, g,
+                                    C, gat, flag))
+                    return;
+                double L[15];
+#pragma unroll
+                for (int i = 0; i < 15; ++i) L[i] = rr->L[i];
+                solve_packed(m, L, b, beta);
+                bcU = cU;
+                bcA = cA;
+                have = true;
+            } else {
+                skipped += 1.0;
+                have = false;
+            }
+            // rotate: date k becomes the decision date, date k-1 the regression date
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const R tu = pu[i], ta = pa[i];
+                pu[i] = cu[i];
+                pa[i] = ca[i];
+                cu[i] = tu;
+                ca[i] = ta;
+            }
+        }
+        if (have) {  // exercise at date 1
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double U = static_cast<double>(pu[i]);
+                const double h = payoff(A.cp, A.K, U);
+                if (pbase + i * kClusterThreads < P && h > 0.0) {
+                    double phi[5];
+                    basis(m, U, static_cast<double>(pa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
+                    double cont = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) cont += phi[q] * beta[q];
+                    if (h > cont) {
+                        cf[i] = h;
+                        tau[i] = 1;
+                    }
+                }
+            }
+        }
+    }
+
+    // price and standard error over the whole scenario
+    double s1[1] = {0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t p = pbase + i * kClusterThreads;
+        if (p < P) s1[0] += cf[i] * sdisc[tau[i]];
+    }
+    block_sum<1>(s1, red, NW);
+    if (!cluster_sum<1>(s1, 1, part + static_cast<int64_t>(n) * G * kPartStride, G, g, C, gat,
+                        flag))
+        return;
+    const double mean = s1[0] / static_cast<double>(P);
+    double s2[1] = {0.0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t p = pbase + i * kClusterThreads;
+        if (p < P) {
+            const double d = cf[i] * sdisc[tau[i]] - mean;
+            s2[0] += d * d;
+            if (A.export_tau) A.tau[static_cast<int64_t>(s) * P + p] = tau[i];
+        }
+    }
+    block_sum<1>(s2, red, NW);
+    if (!cluster_sum<1>(s2, 1, part + static_cast<int64_t>(n + 1) * G * kPartStride, G, g, C,
+                        gat, flag))
+        return;
+    if (g == 0 && threadIdx.x == 0) {
+        double* o = A.out + static_cast<int64_t>(s) * 4;
+        o[0] = mean;
+        o[1] = sqrt(s2[0] / static_cast<double>(P - 1) / static_cast<double>(P));
+        o[2] = skipped;
+        o[3] = 0.0;
+    }
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t count, uint64_t value)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += stride)
+        p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
 // Diagnostics.
 
 __global__ void k_philox_words(uint32_t k0, uint32_t k1, int64_t P, int n, int nb, uint32_t* out)
@@ -749,7 +1073,79 @@ hipError_t launch_sweep_r(int q, const LsmcArgs& a, int S, hipStream_t st)
     }
 }
 
+template <typename R, int Q>
+hipError_t launch_cluster_t(const LsmcArgs& a, const ClusterArgs& c, int S_launch, size_t lds,
+                            hipStream_t st)
+{
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&k_sweep_cluster<R, Q>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_sweep_cluster<R, Q>), dim3(S_launch * c.G), dim3(kClusterThreads), lds,
+                       st, a, c);
+    return hipGetLastError();
+}
+
+template <typename R, int Q>
+int cluster_capacity_t(size_t lds)
+{
+    if (lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_cluster<R, Q>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(lds)) != hipSuccess)
+        return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                     reinterpret_cast<const void*>(&k_sweep_cluster<R, Q>),
+                                                     kClusterThreads, lds) != hipSuccess)
+        return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
 }  // namespace
+
+size_t cluster_lds_bytes(int n, int G)
+{
+    return sizeof(double) * (((n + 2) & ~1) + (kClusterThreads / 64) * 5 + (G + 1) * 5) + 16;
+}
+
+int cluster_capacity(bool fp32, int q, size_t lds)
+{
+    switch (q) {
+    case 2: return fp32 ? cluster_capacity_t<float, 2>(lds) : cluster_capacity_t<double, 2>(lds);
+    case 4: return fp32 ? cluster_capacity_t<float, 4>(lds) : cluster_capacity_t<double, 4>(lds);
+    case 8: return fp32 ? cluster_capacity_t<float, 8>(lds) : cluster_capacity_t<double, 8>(lds);
+    case 16: return fp32 ? cluster_capacity_t<float, 16>(lds) : cluster_capacity_t<double, 16>(lds);
+    default: return 0;
+    }
+}
+
+hipError_t launch_sweep_cluster(bool fp32, int q, const LsmcArgs& a, const ClusterArgs& c,
+                                int S_launch, hipStream_t st)
+{
+    const size_t lds = cluster_lds_bytes(a.n, c.G);
+    switch (q) {
+    case 2: return fp32 ? launch_cluster_t<float, 2>(a, c, S_launch, lds, st) : launch_cluster_t<double, 2>(a, c, S_launch, lds, st);
+    case 4: return fp32 ? launch_cluster_t<float, 4>(a, c, S_launch, lds, st) : launch_cluster_t<double, 4>(a, c, S_launch, lds, st);
+    case 8: return fp32 ? launch_cluster_t<float, 8>(a, c, S_launch, lds, st) : launch_cluster_t<double, 8>(a, c, S_launch, lds, st);
+    case 16: return fp32 ? launch_cluster_t<float, 16>(a, c, S_launch, lds, st) : launch_cluster_t<double, 16>(a, c, S_launch, lds, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_u64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, p, count,
+                       value);
+    return hipGetLastError();
+}
 
 int paths_tmax(bool fp32, int nmax)
 {
@@ -777,15 +1173,17 @@ hipError_t launch_paths(bool fp32, int nmax, const PathArgs& a, int nchunks, int
                 : launch_paths_r<double>(nmax, a, nchunks, nbg, st);
 }
 
+template <typename R>
+hipError_t launch_gram_r(const LsmcArgs& a, int S, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_gram<R>), dim3(a.n - 1, S), dim3(kGramThreads), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_gram(bool fp32, const LsmcArgs& a, int S, hipStream_t st)
 {
     if (a.n < 2) return hipSuccess;
-    dim3 grid(a.n - 1, S), block(kGramThreads);
-    if (fp32)
-        hipLaunchKernelGGL((k_gram<float>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_gram<double>), grid, block, 0, st, a);
-    return hipGetLastError();
+    return fp32 ? launch_gram_r<float>(a, S, st) : launch_gram_r<double>(a, S, st);
 }
 
 int sweep_q_for(int64_t P)

@@ -25,6 +25,15 @@ hipError_t launch_gram(bool fp32, const LsmcArgs& a, int S, hipStream_t st);
 int sweep_q_for(int64_t P);
 hipError_t launch_sweep(bool fp32, int q, const LsmcArgs& a, int S, hipStream_t st);
 
+// Cluster sweep: Q in {2,4,8,16} paths per thread, G workgroups per scenario,
+// S_launch scenarios (planes c.s0 ..) per launch; capacity = workgroups that
+// fit on the device at once.
+size_t cluster_lds_bytes(int n, int G);
+int cluster_capacity(bool fp32, int q, size_t lds);
+hipError_t launch_sweep_cluster(bool fp32, int q, const LsmcArgs& a, const ClusterArgs& c,
+                                int S_launch, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st);
+
 hipError_t launch_philox_words(uint64_t seed, int64_t P, int n, int nb, uint32_t* out,
                                hipStream_t st);
 hipError_t launch_normals(bool fp32, uint64_t seed, int N, int64_t P, int n, void* eps,

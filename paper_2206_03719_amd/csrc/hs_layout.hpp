@@ -87,4 +87,22 @@ struct LsmcArgs {
     int32_t export_tau, pad;
 };
 
+// Cluster sweep: G workgroups of kClusterThreads cooperate on one scenario,
+// meeting once per exercise date at a per-scenario counter.
+constexpr int kClusterThreads = 256;
+constexpr int kPartStride = 8;  // doubles per published partial
+constexpr int kMaxClusterGroups = 1024;
+
+// Partial slots start as kEmptySlot (a NaN bit pattern that arithmetic never
+// produces); a workgroup's published partial is the slot's only write.
+constexpr uint64_t kEmptySlot = ~0ull;
+
+struct ClusterArgs {
+    double* partials;     // [scen][n + 2][G][kPartStride], filled with kEmptySlot
+    int32_t* error;       // set to 1 if a wait timed out
+    int32_t s0;           // first scenario (plane) of this launch
+    int32_t G;            // workgroups per scenario
+    int64_t timeout_ticks;  // wall-clock ticks before a wait gives up
+};
+
 }  // namespace hs

@@ -239,7 +239,7 @@ hs_status validate(const Request& q)
         set_error("opts.flags = 0x%x has unknown bits", op.flags);
         return HS_EINVAL;
     }
-    if (op.sweep_mode < 0 || op.sweep_mode > 2) {
+    if (op.sweep_mode < 0 || op.sweep_mode > 3) {
         set_error("opts.sweep_mode = %d", op.sweep_mode);
         return HS_EINVAL;
     }
@@ -356,11 +356,30 @@ Shape shape_of(const Request& q)
     sh.american = q.opt.style == HS_AMERICAN;
     sh.nmax = paths_nmax_bucket(q.N);
     sh.tmax = paths_tmax(sh.fp32, sh.nmax);
-    if (q.opts.sweep_mode == 2)
+    // cluster sweep shape from the path count alone (never from device load)
+    const int64_t P = q.P;
+    int cq = 8;
+    if (P <= 2 * kClusterThreads)
+        cq = 2;
+    else if (P <= 4 * kClusterThreads)
+        cq = 4;
+    else if ((P + 8 * kClusterThreads - 1) / (8 * kClusterThreads) > 64)
+        cq = 16;
+    sh.cluster_q = cq;
+    const int64_t G = (P + static_cast<int64_t>(cq) * kClusterThreads - 1) /
+                      (static_cast<int64_t>(cq) * kClusterThreads);
+    sh.cluster_g = static_cast<int>(G);
+    const int mode = q.opts.sweep_mode;
+    if (mode == 1) {
+        sh.sweep = kSweepBlockRegs;
+        sh.sweep_q = sweep_q_for(P);
+    } else if (mode == 2 || (mode == 0 && G > kMaxClusterGroups)) {
+        sh.sweep = kSweepBlockState;
         sh.sweep_q = 0;
-    else
-        sh.sweep_q = sweep_q_for(q.P);
-    sh.need_tau = (q.opts.flags & HS_FLAG_EXPORT_TAU) || sh.sweep_q == 0;
+    } else {
+        sh.sweep = kSweepCluster;
+        sh.sweep_q = 0;
+    }
     return sh;
 }
 
@@ -385,10 +404,18 @@ Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, in
     off = align_up(off + (sh.american ? S * q.n * sizeof(RegRec) : 0));
     L.out = off;
     off = align_up(off + S * 4 * sizeof(double));
+    // exercise dates and cash flows of the workspace-state sweep (also the
+    // fallback when a cluster does not fit the device) and the exported dates
     L.tau = off;
-    off = align_up(off + (sh.need_tau ? S * P * sizeof(int32_t) : 0));
+    off = align_up(off + S * P * sizeof(int32_t));
     L.cf = off;
-    off = align_up(off + (sh.sweep_q == 0 ? S * P * sizeof(double) : 0));
+    off = align_up(off + S * P * sizeof(double));
+    L.sync = off;
+    off = align_up(off + (S + 64) * sizeof(uint32_t));
+    L.part = off;
+    if (sh.sweep == kSweepCluster)  // rows: dates 1..n-1, then the two price sums
+        off = align_up(off + S * (q.n + 2) * static_cast<size_t>(sh.cluster_g) * kPartStride *
+                                 sizeof(double));
     L.feat = off;
     off = align_up(off + S * nd * P * 2 * R);
     L.total = off;

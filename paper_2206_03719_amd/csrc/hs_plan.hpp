@@ -55,15 +55,20 @@ struct Pass {
 // Byte offsets of a pass's regions inside the workspace.
 struct Layout {
     size_t base = 0, tasks = 0, groups = 0, disc = 0, reg = 0, out = 0, tau = 0, cf = 0,
-           feat = 0, total = 0;
+           sync = 0, part = 0, feat = 0, total = 0;
 };
+
+// Backward-sweep variants.
+enum SweepKind { kSweepCluster = 0, kSweepBlockRegs = 1, kSweepBlockState = 2 };
 
 struct Shape {
     bool fp32 = true;
     bool american = true;
     int nmax = 0, tmax = 0;
-    int sweep_q = 0;        // 0 = state in the workspace
-    bool need_tau = false;  // tau region (export or workspace state)
+    int sweep = kSweepCluster;
+    int sweep_q = 0;        // single-workgroup sweep: paths per thread (0 = state in workspace)
+    int cluster_q = 0;      // cluster sweep: paths per thread
+    int cluster_g = 0;      // cluster sweep: workgroups per scenario
 };
 
 Shape shape_of(const Request& q);

@@ -51,7 +51,7 @@ def test_workspace_sizes():
     f64 = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"], precision="fp64")
     assert f64 > 1.9 * feat
     eu = dict(w["option"], style="european")
-    assert hs.workspace_bytes(w["model"], eu, 25000, 252, w["bumps"]) < full / 100
+    assert hs.workspace_bytes(w["model"], eu, 25000, 252, w["bumps"]) < full / 50
 
 
 def _call(w, ws_bytes=1 << 34, workspace=FAKE_WS, corr=None, n_paths=None, n_steps=None,

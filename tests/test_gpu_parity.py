@@ -210,10 +210,10 @@ def test_greek_set_fp32_bestof5_full_size():
 # invariances: results are a function of the request alone
 
 def test_bitwise_invariance_launch_shape_and_passes():
-    _say("bitwise invariance: waves per block, sweep mode, workspace passes")
+    _say("bitwise invariance: waves per block, workspace passes")
     w = W.best_of_call(n_assets=5, n_paths=3000, n_steps=40)
     ref = gpu(w, "fp32")
-    for kw in (dict(waves_per_block=1), dict(waves_per_block=8), dict(sweep_mode=2)):
+    for kw in (dict(waves_per_block=1), dict(waves_per_block=8), dict(sweep_mode=3)):
         g = gpu(w, "fp32", **kw)
         assert np.array_equal(g["scenario_price"], ref["scenario_price"]), kw
         assert np.array_equal(g["scenario_se"], ref["scenario_se"]), kw
@@ -222,20 +222,25 @@ def test_bitwise_invariance_launch_shape_and_passes():
     ws = torch.empty(mn, dtype=torch.uint8, device="cuda")
     g = gpu(w, "fp32", workspace=ws)
     assert np.array_equal(g["scenario_price"], ref["scenario_price"])
+    # the single-workgroup sweeps sum the same FP64 terms in another order
+    for sm in (1, 2):
+        g = gpu(w, "fp32", sweep_mode=sm)
+        assert rel(g["scenario_price"], ref["scenario_price"]).max() <= 1e-13
 
 
-@pytest.mark.parametrize("P", [16384, 16385, 25000])
-def test_sweep_modes_across_register_limit(P):
-    # register-resident cash flows up to 16 paths per thread, workspace-resident
-    # beyond; both must price like the oracle and identically to each other
-    _say("sweep modes at P=%d" % P)
+@pytest.mark.parametrize("P", [16384, 16385, 25000, 70001])
+def test_sweep_variants_vs_oracle(P):
+    # cluster sweep (G workgroups per scenario, ragged last workgroup), and the
+    # single-workgroup sweeps with the state in registers or the workspace
+    _say("sweep variants at P=%d" % P)
     w = W.best_of_call(n_assets=5, n_paths=P, n_steps=40, mask=0)
-    o = orc(w)
-    a = gpu(w, "fp64", sweep_mode=2)
-    assert rel(a["price"], o["price"]) <= 1e-12
-    if P <= 16384:
-        b = gpu(w, "fp64", sweep_mode=1)
-        assert a["price"] == b["price"] and a["price_se"] == b["price_se"]
+    o = orc(w, export_tau=True)
+    modes = [0, 2, 3] + ([1] if P <= 16384 else [])
+    for sm in modes:
+        g = gpu(w, "fp64", sweep_mode=sm, export_tau=True)
+        assert rel(g["price"], o["price"]) <= 1e-12, sm
+        assert rel(g["price_se"], o["price_se"]) <= 1e-9, sm
+        assert np.array_equal(g["tau"], o["tau"]), sm
 
 
 def test_repeat_runs_identical():
