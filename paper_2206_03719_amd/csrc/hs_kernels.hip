@@ -339,30 +339,78 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// FP64 block reductions with a fixed tree: xor butterfly inside each wave
-// (every lane ends with the same bits), then the waves' sums in index order.
+// FP64 block reductions with a fixed tree.  Inside a wave: DPP row shifts by
+// 1, 2, 4, 8 (each lane adds its row neighbour; lanes past the row start add
+// 0), then the row broadcasts of lanes 15 and 31, leaving the wave's total in
+// lane 63.  Across waves: K threads fold the wave totals in wave order.  The
+// order of every addition is fixed, so the sum is deterministic.
+
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_tag)
+{
+    const uint64_t bits = __builtin_bit_cast(uint64_t, v);
+    int lo = static_cast<int>(bits), hi = static_cast<int>(bits >> 32);
+    switch (ctrl_tag) {
+    case 1:
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, true);
+        break;
+    case 2:
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, true);
+        break;
+    case 4:
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, true);
+        break;
+    case 8:
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, true);
+        break;
+    case 15:  // row_bcast15 into rows 1 and 3
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false);
+        break;
+    default:  // row_bcast31 into rows 2 and 3
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false);
+        break;
+    }
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(lo));
+}
+
+// The wave's total, valid in lane 63.
+__device__ __forceinline__ double wave_sum_lane63(double v)
+{
+    v += dpp_f64(v, 1);
+    v += dpp_f64(v, 2);
+    v += dpp_f64(v, 4);
+    v += dpp_f64(v, 8);
+    v += dpp_f64(v, 15);
+    v += dpp_f64(v, 31);
+    return v;
+}
 
 template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double* scratch /* [nwaves][K] */,
+__device__ __forceinline__ void block_sum(double (&v)[K], double* scratch /* [nwaves][K] + K */,
                                           int nwaves)
 {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < K; ++i) v[i] += __shfl_xor(v[i], off, 64);
-    }
+    for (int i = 0; i < K; ++i) v[i] = wave_sum_lane63(v[i]);
     const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    if ((threadIdx.x & 63) == 63) {
 #pragma unroll
         for (int i = 0; i < K; ++i) scratch[wid * K + i] = v[i];
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        double s = scratch[i];
-        for (int q = 1; q < nwaves; ++q) s += scratch[q * K + i];
-        v[i] = s;
+    if (threadIdx.x < K) {
+        double s = scratch[threadIdx.x];
+        for (int q = 1; q < nwaves; ++q) s += scratch[q * K + threadIdx.x];
+        scratch[nwaves * K + threadIdx.x] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] = scratch[nwaves * K + i];
     __syncthreads();
 }
 
@@ -411,8 +459,28 @@ __device__ __forceinline__ void gram_finish(int m, const double (&g)[15], double
             }
         }
     }
+    // store the inverse factor, so a solve is two triangular mat-vecs:
+    // beta = L^{-T} (L^{-1} b)
+    double Li[15];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) rr->L[i] = ok ? L[i] : 0.0;
+    for (int i = 0; i < 15; ++i) Li[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        if (j < m) {
+            Li[j * (j + 1) / 2 + j] = 1.0 / L[j * (j + 1) / 2 + j];
+#pragma unroll
+            for (int i = j + 1; i < 5; ++i) {
+                if (i < m) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int q = j; q < i; ++q) acc += L[i * (i + 1) / 2 + q] * Li[q * (q + 1) / 2 + j];
+                    Li[i * (i + 1) / 2 + j] = -acc / L[i * (i + 1) / 2 + i];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 15; ++i) rr->L[i] = ok ? Li[i] : 0.0;
     rr->cU = cU;
     rr->cA = cA;
     rr->ok = ok ? 1.0 : 0.0;
@@ -426,7 +494,7 @@ template <typename R>
 __global__ void __launch_bounds__(kGramThreads) k_gram(const LsmcArgs A)
 {
     constexpr int U1 = 8, U2 = 4;  // loads in flight per thread in the two passes
-    __shared__ double red[(kGramThreads / 64) * 15];
+    __shared__ double red[(kGramThreads / 64 + 1) * 15];
     const int s = blockIdx.y;
     const int k = blockIdx.x + 1;
     const R2<R>* __restrict__ F =
@@ -508,25 +576,26 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const LsmcArgs A)
 // handles paths t + 1024 i.  With GLB the cash flow and exercise date of each
 // path live in the workspace; otherwise in registers (Q paths per thread).
 
-// L L^T beta = b with L packed lower row-major (m = 3 or 5); the entries of
-// beta past m are 0.
-__device__ __forceinline__ void solve_packed(int m, const double (&L)[15], const double (&b)[5],
+// beta = L^{-T} (L^{-1} b) with Li = L^{-1} packed lower row-major (entries
+// past m are 0, so beta past m is 0).
+__device__ __forceinline__ void solve_packed(int m, const double (&Li)[15], const double (&b)[5],
                                              double (&beta)[5])
 {
+    (void)m;
     double y[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        double acc = b[i];
+        double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < i; ++q) acc -= L[i * (i + 1) / 2 + q] * y[q];
-        y[i] = i < m ? acc / L[i * (i + 1) / 2 + i] : 0.0;
+        for (int q = 0; q <= i; ++q) acc += Li[i * (i + 1) / 2 + q] * b[q];
+        y[i] = acc;
     }
 #pragma unroll
-    for (int i = 4; i >= 0; --i) {
-        double acc = y[i];
+    for (int i = 0; i < 5; ++i) {
+        double acc = 0.0;
 #pragma unroll
-        for (int q = i + 1; q < 5; ++q) acc -= L[q * (q + 1) / 2 + i] * beta[q];
-        beta[i] = i < m ? acc / L[i * (i + 1) / 2 + i] : 0.0;
+        for (int q = i; q < 5; ++q) acc += Li[q * (q + 1) / 2 + i] * y[q];
+        beta[i] = acc;
     }
 }
 
@@ -535,7 +604,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
 {
     extern __shared__ unsigned char hs_smem[];
     double* const sdisc = reinterpret_cast<double*>(hs_smem);         // [n+1]
-    double* const red = sdisc + ((A.n + 1 + 1) & ~1);                 // [16][5]
+    double* const red = sdisc + ((A.n + 1 + 1) & ~1);                 // [16 + 1][5]
     constexpr int NW = kSweepThreads / 64;
     const int s = blockIdx.x;
     const int n = A.n;
@@ -767,8 +836,8 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     const int n = A.n;
     const int G = C.G;
     double* const sdisc = reinterpret_cast<double*>(hs_smem);  // [n+1]
-    double* const red = sdisc + ((n + 2) & ~1);                 // [NW][5]
-    double* const gat = red + NW * 5;                           // [G+1][5]
+    double* const red = sdisc + ((n + 2) & ~1);                 // [NW + 1][5]
+    double* const gat = red + (NW + 1) * 5;                     // [G+1][5]
     int* const flag = reinterpret_cast<int*>(gat + (G + 1) * 5);
     const int sl = blockIdx.x / G;
     const int g = blockIdx.x - sl * G;
@@ -799,25 +868,32 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     double bcU = 0.0, bcA = 0.0;
     bool have = false;  // beta of the later date k+1 is valid
     double skipped = 0.0;
-    // cu/ca: features of date k (this iteration's regression); pu/pa: features
-    // of date k+1 for its exercise decision, then the prefetch of date k-1
-    R cu[Q], ca[Q], pu[Q], pa[Q];
+    // pu/pa: features of date k+1 (its exercise decision); cu/ca: date k (this
+    // iteration's regression); nu/na: date k-1, loaded one iteration ago; the
+    // loads of date k-2 are issued during this iteration's exchange.
+    R cu[Q], ca[Q], pu[Q], pa[Q], nu[Q], na[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         pu[i] = R(0);
         pa[i] = R(0);
         cu[i] = R(0);
         ca[i] = R(0);
+        nu[i] = R(0);
+        na[i] = R(0);
     }
-    if (A.american && n >= 2) {
-        const R2<R>* __restrict__ F0 = F + static_cast<int64_t>(n - 2) * P;
+    if (A.american) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int64_t p = pbase + i * kClusterThreads;
-            if (p < P) {
-                const R2<R> f = F0[p];
+            if (p < P && n >= 2) {
+                const R2<R> f = F[static_cast<int64_t>(n - 2) * P + p];
                 cu[i] = f.u;
                 ca[i] = f.a;
+            }
+            if (p < P && n >= 3) {
+                const R2<R> f = F[static_cast<int64_t>(n - 3) * P + p];
+                nu[i] = f.u;
+                na[i] = f.a;
             }
         }
     }
@@ -870,9 +946,10 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
                 }
                 block_sum<5>(b, red, NW);
             }
-            // prefetch date k-1 while the scenario's workgroups meet
-            if (k > 1) {
-                const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 2) * P;
+            // date k+1 is decided: its registers take date k-2, loaded while
+            // the scenario's workgroups meet
+            if (k > 2) {
+                const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 3) * P;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     const int64_t p = pbase + i * kClusterThreads;
@@ -898,14 +975,17 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
                 skipped += 1.0;
                 have = false;
             }
-            // rotate: date k becomes the decision date, date k-1 the regression date
+            // rotate: k becomes the decision date, k-1 the regression date, and
+            // the k-2 loads the next prefetched date
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const R tu = pu[i], ta = pa[i];
                 pu[i] = cu[i];
                 pa[i] = ca[i];
-                cu[i] = tu;
-                ca[i] = ta;
+                cu[i] = nu[i];
+                ca[i] = na[i];
+                nu[i] = tu;
+                na[i] = ta;
             }
         }
         if (have) {  // exercise at date 1
@@ -1054,7 +1134,7 @@ hipError_t launch_paths_r(int nmax, const PathArgs& a, int nchunks, int nbg, hip
 template <typename R, int Q, bool GLB>
 hipError_t launch_sweep_t(const LsmcArgs& a, int S, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * (((a.n + 2) & ~1) + (kSweepThreads / 64) * 5);
+    const size_t lds = sizeof(double) * (((a.n + 2) & ~1) + (kSweepThreads / 64 + 1) * 5);
     hipLaunchKernelGGL((k_sweep<R, Q, GLB>), dim3(S), dim3(kSweepThreads), lds, st, a);
     return hipGetLastError();
 }
@@ -1111,16 +1191,16 @@ int cluster_capacity_t(size_t lds)
 
 size_t cluster_lds_bytes(int n, int G)
 {
-    return sizeof(double) * (((n + 2) & ~1) + (kClusterThreads / 64) * 5 + (G + 1) * 5) + 16;
+    return sizeof(double) * (((n + 2) & ~1) + (kClusterThreads / 64 + 1) * 5 + (G + 1) * 5) + 16;
 }
 
 int cluster_capacity(bool fp32, int q, size_t lds)
 {
     switch (q) {
+    case 1: return fp32 ? cluster_capacity_t<float, 1>(lds) : cluster_capacity_t<double, 1>(lds);
     case 2: return fp32 ? cluster_capacity_t<float, 2>(lds) : cluster_capacity_t<double, 2>(lds);
     case 4: return fp32 ? cluster_capacity_t<float, 4>(lds) : cluster_capacity_t<double, 4>(lds);
     case 8: return fp32 ? cluster_capacity_t<float, 8>(lds) : cluster_capacity_t<double, 8>(lds);
-    case 16: return fp32 ? cluster_capacity_t<float, 16>(lds) : cluster_capacity_t<double, 16>(lds);
     default: return 0;
     }
 }
@@ -1130,10 +1210,10 @@ hipError_t launch_sweep_cluster(bool fp32, int q, const LsmcArgs& a, const Clust
 {
     const size_t lds = cluster_lds_bytes(a.n, c.G);
     switch (q) {
+    case 1: return fp32 ? launch_cluster_t<float, 1>(a, c, S_launch, lds, st) : launch_cluster_t<double, 1>(a, c, S_launch, lds, st);
     case 2: return fp32 ? launch_cluster_t<float, 2>(a, c, S_launch, lds, st) : launch_cluster_t<double, 2>(a, c, S_launch, lds, st);
     case 4: return fp32 ? launch_cluster_t<float, 4>(a, c, S_launch, lds, st) : launch_cluster_t<double, 4>(a, c, S_launch, lds, st);
     case 8: return fp32 ? launch_cluster_t<float, 8>(a, c, S_launch, lds, st) : launch_cluster_t<double, 8>(a, c, S_launch, lds, st);
-    case 16: return fp32 ? launch_cluster_t<float, 16>(a, c, S_launch, lds, st) : launch_cluster_t<double, 16>(a, c, S_launch, lds, st);
     default: return hipErrorInvalidValue;
     }
 }

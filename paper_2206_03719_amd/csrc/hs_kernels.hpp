@@ -25,7 +25,7 @@ hipError_t launch_gram(bool fp32, const LsmcArgs& a, int S, hipStream_t st);
 int sweep_q_for(int64_t P);
 hipError_t launch_sweep(bool fp32, int q, const LsmcArgs& a, int S, hipStream_t st);
 
-// Cluster sweep: Q in {2,4,8,16} paths per thread, G workgroups per scenario,
+// Cluster sweep: Q in {1,2,4,8} paths per thread, G workgroups per scenario,
 // S_launch scenarios (planes c.s0 ..) per launch; capacity = workgroups that
 // fit on the device at once.
 size_t cluster_lds_bytes(int n, int G);

@@ -64,8 +64,8 @@ struct PathArgs {
     uint32_t key0, key1;
 };
 
-// Regression record of one (scenario, date): packed lower Cholesky factor of
-// the Gram matrix (m(m+1)/2 entries), reciprocals of its diagonal, the
+// Regression record of one (scenario, date): the inverse of the lower
+// Cholesky factor of the Gram matrix, packed row-major (m(m+1)/2 entries), the
 // regression-set means, ok flag and set size.
 struct RegRec {
     double L[15];
@@ -89,7 +89,7 @@ struct LsmcArgs {
 
 // Cluster sweep: G workgroups of kClusterThreads cooperate on one scenario,
 // meeting once per exercise date at a per-scenario counter.
-constexpr int kClusterThreads = 256;
+constexpr int kClusterThreads = 512;
 constexpr int kPartStride = 8;  // doubles per published partial
 constexpr int kMaxClusterGroups = 1024;
 

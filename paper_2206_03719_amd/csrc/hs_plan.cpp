@@ -359,12 +359,12 @@ Shape shape_of(const Request& q)
     // cluster sweep shape from the path count alone (never from device load)
     const int64_t P = q.P;
     int cq = 8;
-    if (P <= 2 * kClusterThreads)
+    if (P <= kClusterThreads)
+        cq = 1;
+    else if (P <= 2 * kClusterThreads)
         cq = 2;
     else if (P <= 4 * kClusterThreads)
         cq = 4;
-    else if ((P + 8 * kClusterThreads - 1) / (8 * kClusterThreads) > 64)
-        cq = 16;
     sh.cluster_q = cq;
     const int64_t G = (P + static_cast<int64_t>(cq) * kClusterThreads - 1) /
                       (static_cast<int64_t>(cq) * kClusterThreads);
