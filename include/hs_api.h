@@ -93,6 +93,9 @@ typedef int32_t hs_status;
 /* opts.flags */
 #define HS_FLAG_EXPORT_TAU 1u /* write each path's exercise date into greeks.tau */
 #define HS_FLAG_TIMING 2u     /* fill greeks.t_*_ms with per-stage device times  */
+#define HS_FLAG_GRAPH 4u      /* run each pass as a hipGraph: captured once per
+                                 launch shape and workspace, then replayed (needs a
+                                 non-null stream; ignored with HS_FLAG_TIMING)      */
 
 typedef struct hs_model {
     int32_t n_assets;       /* 1..HS_MAX_ASSETS                                */
@@ -208,6 +211,19 @@ hs_status hs_path_features(const hs_model *model, const double *corr, int64_t n_
                            int32_t n_steps, double T, const hs_opts *opts, void *d_out,
                            size_t out_bytes, void *d_workspace, size_t workspace_bytes,
                            void *hip_stream);
+
+/* Autotuner of the path kernel's launch shape (waves per block, scenario-group
+ * granularity) for requests shaped like this one: times each candidate
+ * `repeats` times on hip_stream with the given workspace and stores the
+ * fastest in a process-wide table that hs_price_greeks and the server consult
+ * when opts.waves_per_block == 0.  These parameters never change results (the
+ * backward-sweep shape, which does fix the order of FP64 sums, depends on
+ * n_paths alone and is not tuned).  *best_ms (host, may be NULL) receives the
+ * winning Greek-set time.  Same arguments and errors as hs_price_greeks. */
+hs_status hs_autotune(const hs_model *model, const double *corr, const hs_option *option,
+                      int64_t n_paths, int32_t n_steps, const hs_bumps *bumps,
+                      const hs_opts *opts, void *d_workspace, size_t workspace_bytes,
+                      void *hip_stream, int32_t repeats, double *best_ms);
 
 /* Diagnostics for bit-exactness checks of the device random numbers.
  * hs_philox_words: d_out (device uint32) receives, for path p in

@@ -21,7 +21,7 @@ SINGLE, MAX_OF = 0, 1
 BASIS_AUTO, BASIS_QUAD, BASIS_QUAD_VOL = 0, 1, 2
 BUMP_DELTA_GAMMA, BUMP_VEGA, BUMP_THETA, BUMP_RHO, BUMP_CORR, BUMP_ALL = 1, 2, 4, 8, 16, 31
 FP64, FP32_PATHS = 0, 1
-FLAG_EXPORT_TAU, FLAG_TIMING = 1, 2
+FLAG_EXPORT_TAU, FLAG_TIMING, FLAG_GRAPH = 1, 2, 4
 MAX_ASSETS = 20
 
 _CP = {"put": PUT, "call": CALL}
@@ -102,6 +102,11 @@ _SIGS = {
                                          ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Bumps),
                                          ctypes.POINTER(Opts), ctypes.c_void_p, ctypes.c_size_t,
                                          ctypes.c_void_p, ctypes.POINTER(Greeks)]),
+    "hs_autotune": (ctypes.c_int32, [ctypes.POINTER(Model), _dp, ctypes.POINTER(Option),
+                                     ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Bumps),
+                                     ctypes.POINTER(Opts), ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_double)]),
     "hs_path_features_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "hs_path_features": (ctypes.c_int32, [ctypes.POINTER(Model), _dp, ctypes.c_int64,
                                           ctypes.c_int32, ctypes.c_double, ctypes.POINTER(Opts),
@@ -211,13 +216,15 @@ def _stream_handle(stream):
 
 def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="fp32",
                  workspace=None, stream=None, export_tau=False, timing=False,
-                 waves_per_block=0, sweep_mode=0):
+                 waves_per_block=0, sweep_mode=0, graph=False):
     """Price + bump-and-revalue Greeks of one option (hs_price_greeks).
 
-    ``workspace``: a CUDA uint8 tensor (allocated here when None).  Returns a
-    dict of numpy arrays / floats."""
+    ``workspace``: a CUDA uint8 tensor (allocated here when None).  ``graph``:
+    replay the pass's kernels from a cached HIP graph.  Returns a dict of numpy
+    arrays / floats."""
     torch = _torch()
-    flags = (FLAG_EXPORT_TAU if export_tau else 0) | (FLAG_TIMING if timing else 0)
+    flags = ((FLAG_EXPORT_TAU if export_tau else 0) | (FLAG_TIMING if timing else 0) |
+             (FLAG_GRAPH if graph else 0))
     m = _Marshal(model, corr, option, bumps, seed, precision, flags, waves_per_block, sweep_mode)
     N = m.N
     if workspace is None:
@@ -249,6 +256,24 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precisio
     if tau is not None:
         res["tau"] = tau
     return res
+
+
+def autotune(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="fp32",
+             workspace=None, stream=None, repeats=3):
+    """Times the path kernel's launch shapes on this request class and stores
+    the fastest for later calls (hs_autotune).  Returns the best ms per set."""
+    torch = _torch()
+    m = _Marshal(model, corr, option, bumps, seed, precision)
+    if workspace is None:
+        nbytes = workspace_bytes(model, option, n_paths, n_steps, bumps, precision)
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    best = ctypes.c_double(0.0)
+    _check(lib().hs_autotune(ctypes.byref(m.model), m.corr_ptr, ctypes.byref(m.option),
+                             int(n_paths), int(n_steps), ctypes.byref(m.bumps),
+                             ctypes.byref(m.opts), ctypes.c_void_p(workspace.data_ptr()),
+                             workspace.numel() * workspace.element_size(),
+                             _stream_handle(stream), int(repeats), ctypes.byref(best)))
+    return best.value
 
 
 def path_features(model, corr, T, n_paths, n_steps, seed=42, precision="fp64", stream=None):

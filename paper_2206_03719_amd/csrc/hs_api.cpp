@@ -3,9 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
 #include <numeric>
 #include <vector>
 
@@ -54,8 +58,157 @@ double mean_theta(const Request& q)
 
 int default_target_waves() { return 2048; }
 
+// ---------------------------------------------------------------------------
+// Tuning table: launch shape of the path kernel per request class.
+
+namespace {
+
+struct TuneKey {
+    int N, log2P, n_bucket, S, fp32;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(N, log2P, n_bucket, S, fp32) < std::tie(o.N, o.log2P, o.n_bucket, o.S, o.fp32);
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, Tune> g_tune;
+
+TuneKey tune_key(const Request& q)
+{
+    int lp = 0;
+    while ((int64_t(1) << (lp + 1)) <= q.P) ++lp;
+    int nb = 0;
+    while ((1 << (nb + 1)) <= q.n) ++nb;
+    return {q.N, lp, nb, static_cast<int>(num_scenarios(q.N, q.bumps.mask)),
+            q.opts.precision == HS_FP32_PATHS ? 1 : 0};
+}
+
+// ---------------------------------------------------------------------------
+// Graph cache: one instantiated graph per (device, workspace, launch arguments).
+
+std::mutex g_graph_mu;
+std::map<std::string, hipGraphExec_t> g_graphs;
+constexpr size_t kMaxGraphs = 128;
+
+template <typename T>
+void append_bytes(std::string& k, const T& v)
+{
+    k.append(reinterpret_cast<const char*>(&v), sizeof v);
+}
+
+// Everything one pass enqueues after its tables are uploaded.
+struct PassLaunch {
+    bool fp32 = true, american = true, cluster = false;
+    int nmax = 0, nchunks = 0, nbg = 0, Sp = 0, cluster_q = 0, per_launch = 0, sweep_q = 0;
+    int64_t part_count = 0;
+    PathArgs pa{};
+    LsmcArgs la{};
+    ClusterArgs ca{};
+    int32_t* err_flag = nullptr;
+};
+
+hipError_t enqueue_pass(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
+{
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.err_flag), 1, 0, st)) != hipSuccess)
+        return e;
+    if ((e = launch_paths(L.fp32, L.nmax, L.pa, L.nchunks, L.nbg, st)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+    if (L.american && (e = launch_gram(L.fp32, L.la, L.Sp, st)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+    if (L.cluster) {
+        if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.ca.partials), L.part_count,
+                                 kEmptySlot, st)) != hipSuccess)
+            return e;
+        ClusterArgs ca = L.ca;
+        for (int s0 = 0; s0 < L.Sp; s0 += L.per_launch) {
+            ca.s0 = s0;
+            if ((e = launch_sweep_cluster(L.fp32, L.cluster_q, L.la, ca,
+                                          std::min(L.per_launch, L.Sp - s0), st)) != hipSuccess)
+                return e;
+        }
+    } else {
+        if ((e = launch_sweep(L.fp32, L.sweep_q, L.la, L.Sp, st)) != hipSuccess) return e;
+    }
+    if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t launch_pass_graph(const PassLaunch& L, void* ws, hipStream_t st)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::string key;
+    append_bytes(key, dev);
+    append_bytes(key, ws);
+    append_bytes(key, L.fp32);
+    append_bytes(key, L.american);
+    append_bytes(key, L.cluster);
+    append_bytes(key, L.nmax);
+    append_bytes(key, L.nchunks);
+    append_bytes(key, L.nbg);
+    append_bytes(key, L.Sp);
+    append_bytes(key, L.cluster_q);
+    append_bytes(key, L.per_launch);
+    append_bytes(key, L.sweep_q);
+    append_bytes(key, L.part_count);
+    append_bytes(key, L.pa);
+    append_bytes(key, L.la);
+    append_bytes(key, L.ca);
+    append_bytes(key, L.err_flag);
+    // held through capture and launch, so no other thread evicts an exec that
+    // is about to be launched
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    hipGraphExec_t exec = nullptr;
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) exec = it->second;
+    if (!exec) {
+        if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+        const hipError_t eq = enqueue_pass(L, st, nullptr);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(st, &graph);
+        if (eq != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return eq;
+        }
+        if (e != hipSuccess) return e;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        if (g_graphs.size() >= kMaxGraphs) {
+            // execs already launched on other streams must finish first
+            if ((e = hipDeviceSynchronize()) != hipSuccess) {
+                (void)hipGraphExecDestroy(exec);
+                return e;
+            }
+            for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+            g_graphs.clear();
+        }
+        g_graphs.emplace(key, exec);
+    }
+    return hipGraphLaunch(exec, st);
+}
+
+}  // namespace
+
+Tune tuned_shape(const Request& q)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(q));
+    return it == g_tune.end() ? Tune{} : it->second;
+}
+
+void store_tuned_shape(const Request& q, const Tune& t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(q)] = t;
+}
+
 hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream_t st,
-                        RunResult& res, int target_waves)
+                        RunResult& res, const Tune* tune)
 {
     std::vector<Scenario> sc;
     hs_status rc = expand_scenarios(q, sc);
@@ -71,6 +224,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         set_error("workspace must be 256-byte aligned");
         return HS_EINVAL;
     }
+    const Tune tn = tune ? *tune : tuned_shape(q);
     const size_t S = sc.size();
     res.price.assign(S, 0.0);
     res.se.assign(S, 0.0);
@@ -80,6 +234,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
     res.n_passes = static_cast<int>(passes.size());
 
     const bool timing = (q.opts.flags & HS_FLAG_TIMING) != 0;
+    const bool graph = !timing && (q.opts.flags & HS_FLAG_GRAPH) && st != nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (timing)
         for (auto& e : ev) HS_HIP(hipEventCreate(&e), "hipEventCreate");
@@ -95,9 +250,9 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
     unsigned char* ws = static_cast<unsigned char*>(d_ws);
     const int m = basis_m(q);
     const double tbar = mean_theta(q);
-    const int tw = target_waves > 0 ? target_waves : default_target_waves();
+    const int tw = tn.target_waves > 0 ? tn.target_waves : default_target_waves();
     for (const Pass& pass : passes) {
-        const PassPlan pp = plan_pass(q, sh, sc, pass, tw);
+        const PassPlan pp = plan_pass(q, sh, sc, pass, tw, tn.wmax);
         if (pp.lay.total > ws_bytes) {
             set_error("internal: pass needs %zu bytes of a %zu-byte workspace", pp.lay.total,
                       ws_bytes);
@@ -120,7 +275,16 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         HS_HIP(hipMemcpyAsync(ws + pp.lay.disc, pp.disc.data(), pp.disc.size() * sizeof(double),
                               hipMemcpyHostToDevice, st), "upload discounts");
 
-        PathArgs pa{};
+        PassLaunch L;
+        // zero padding too: the graph cache keys on these bytes
+        std::memset(static_cast<void*>(&L), 0, sizeof L);
+        L.fp32 = sh.fp32;
+        L.american = sh.american;
+        L.nmax = sh.nmax;
+        L.nchunks = pp.nchunks;
+        L.nbg = pp.nbg;
+        L.Sp = Sp;
+        PathArgs& pa = L.pa;
         pa.base = ws + pp.lay.base;
         pa.tasks = ws + pp.lay.tasks;
         pa.groups = reinterpret_cast<const GroupP*>(ws + pp.lay.groups);
@@ -134,7 +298,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         pa.key0 = static_cast<uint32_t>(q.opts.seed);
         pa.key1 = static_cast<uint32_t>(q.opts.seed >> 32);
 
-        LsmcArgs la{};
+        LsmcArgs& la = L.la;
         la.feat = pa.feat;
         la.reg = reinterpret_cast<RegRec*>(ws + pp.lay.reg);
         la.disc = reinterpret_cast<const double*>(ws + pp.lay.disc);
@@ -152,19 +316,12 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         la.inv_tbar = 1.0 / tbar;
         la.export_tau = (q.opts.flags & HS_FLAG_EXPORT_TAU) ? 1 : 0;
 
-        if (timing) HS_HIP(hipEventRecord(ev[0], st), "hipEventRecord");
-        HS_HIP(launch_paths(sh.fp32, sh.nmax, pa, pp.nchunks, pp.nbg, st), "path kernel launch");
-        if (timing) HS_HIP(hipEventRecord(ev[1], st), "hipEventRecord");
-        if (sh.american) HS_HIP(launch_gram(sh.fp32, la, Sp, st), "Gram kernel launch");
-        if (timing) HS_HIP(hipEventRecord(ev[2], st), "hipEventRecord");
         // backward sweep: a cluster of workgroups per scenario when it fits the
         // device, else one workgroup per scenario with the state in the workspace
-        std::unique_lock<std::mutex> cluster_lock(g_cluster_mu, std::defer_lock);
-        uint32_t* sync = reinterpret_cast<uint32_t*>(ws + pp.lay.sync);
-        int32_t* err_flag = reinterpret_cast<int32_t*>(sync);
-        bool cluster = sh.sweep == kSweepCluster;
+        L.err_flag = reinterpret_cast<int32_t*>(ws + pp.lay.sync);
+        L.cluster = sh.sweep == kSweepCluster;
         int cap = 0;
-        if (cluster) {
+        if (L.cluster) {
             cap = cluster_capacity(sh.fp32, sh.cluster_q, cluster_lds_bytes(q.n, sh.cluster_g));
             if (cap < sh.cluster_g) {
                 if (q.opts.sweep_mode == 3) {
@@ -172,38 +329,31 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
                               sh.cluster_g, cap);
                     return HS_EDEVICE;
                 }
-                cluster = false;
+                L.cluster = false;
             }
         }
-        HS_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(sync), 1, 0, st), "clear sweep status");
-        if (cluster) {
-            HS_HIP(launch_fill_u64(reinterpret_cast<uint64_t*>(ws + pp.lay.part),
-                                   static_cast<int64_t>(Sp) * (q.n + 2) * sh.cluster_g * kPartStride,
-                                   kEmptySlot, st), "clear partial slots");
-            ClusterArgs ca{};
-            ca.partials = reinterpret_cast<double*>(ws + pp.lay.part);
-            ca.error = err_flag;
-            ca.G = sh.cluster_g;
-            ca.timeout_ticks = wall_clock_ticks(10.0);
-            const int per_launch = std::max(1, cap / sh.cluster_g);
-            cluster_lock.lock();
-            for (int s0 = 0; s0 < Sp; s0 += per_launch) {
-                ca.s0 = s0;
-                HS_HIP(launch_sweep_cluster(sh.fp32, sh.cluster_q, la, ca,
-                                            std::min(per_launch, Sp - s0), st),
-                       "cluster sweep launch");
-            }
-        } else {
-            const int qreg = sh.sweep == kSweepBlockRegs ? sh.sweep_q : 0;
-            HS_HIP(launch_sweep(sh.fp32, qreg, la, Sp, st), "sweep kernel launch");
+        L.sweep_q = sh.sweep == kSweepBlockRegs ? sh.sweep_q : 0;
+        if (L.cluster) {
+            L.cluster_q = sh.cluster_q;
+            L.per_launch = std::max(1, cap / sh.cluster_g);
+            L.part_count = static_cast<int64_t>(Sp) * (q.n + 2) * sh.cluster_g * kPartStride;
+            L.ca.partials = reinterpret_cast<double*>(ws + pp.lay.part);
+            L.ca.error = L.err_flag;
+            L.ca.G = sh.cluster_g;
+            L.ca.timeout_ticks = wall_clock_ticks(10.0);
         }
-        if (timing) HS_HIP(hipEventRecord(ev[3], st), "hipEventRecord");
+        std::unique_lock<std::mutex> cluster_lock(g_cluster_mu, std::defer_lock);
+        if (L.cluster) cluster_lock.lock();
+        if (graph)
+            HS_HIP(launch_pass_graph(L, ws, st), "graph launch");
+        else
+            HS_HIP(enqueue_pass(L, st, timing ? ev : nullptr), "kernel launch");
 
         std::vector<double> out(static_cast<size_t>(Sp) * 4);
         int32_t err_host = 0;
         HS_HIP(hipMemcpyAsync(out.data(), la.out, out.size() * sizeof(double),
                               hipMemcpyDeviceToHost, st), "download results");
-        HS_HIP(hipMemcpyAsync(&err_host, err_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+        HS_HIP(hipMemcpyAsync(&err_host, L.err_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st),
                "download sweep status");
         std::vector<int32_t> tau;
         if (la.export_tau) {
@@ -214,7 +364,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         HS_HIP(hipStreamSynchronize(st), "stream synchronize");
         if (cluster_lock.owns_lock()) cluster_lock.unlock();
         if (err_host != 0) {
-            set_error("cluster sweep: a workgroup barrier timed out (device oversubscribed?)");
+            set_error("cluster sweep: a workgroup wait timed out (device oversubscribed?)");
             return HS_EDEVICE;
         }
         for (int i = 0; i < Sp; ++i) {
@@ -331,9 +481,53 @@ hs_status hs_price_greeks(const hs_model* model, const double* corr, const hs_op
     if (rc != HS_OK) return rc;
     RunResult res;
     rc = run_greek_set(q, d_workspace, workspace_bytes, static_cast<hipStream_t>(hip_stream), res,
-                       0);
+                       nullptr);
     if (rc != HS_OK) return rc;
     fill_greeks(q, res, out);
+    return HS_OK;
+}
+
+hs_status hs_autotune(const hs_model* model, const double* corr, const hs_option* option,
+                      int64_t n_paths, int32_t n_steps, const hs_bumps* bumps,
+                      const hs_opts* opts, void* d_workspace, size_t workspace_bytes,
+                      void* hip_stream, int32_t repeats, double* best_ms)
+{
+    if (!d_workspace || repeats < 1 || repeats > 100) {
+        set_error("hs_autotune: null workspace or repeats outside 1..100");
+        return HS_EINVAL;
+    }
+    Request q;
+    hs_status rc = copy_request(model, corr, option, n_paths, n_steps, bumps, opts, q);
+    if (rc != HS_OK) return rc;
+    rc = validate(q);
+    if (rc != HS_OK) return rc;
+    q.opts.flags &= ~(HS_FLAG_TIMING | HS_FLAG_EXPORT_TAU | HS_FLAG_GRAPH);
+    q.opts.waves_per_block = 0;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    static const int waves[] = {1024, 2048, 4096, 8192};
+    static const int wmaxes[] = {4, 8};
+    Tune best{};
+    double best_t = 1e300;
+    for (int tw : waves)
+        for (int wm : wmaxes) {
+            const Tune t{tw, wm};
+            RunResult res;
+            rc = run_greek_set(q, d_workspace, workspace_bytes, st, res, &t);  // warm-up
+            if (rc != HS_OK) return rc;
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int r = 0; r < repeats; ++r) {
+                rc = run_greek_set(q, d_workspace, workspace_bytes, st, res, &t);
+                if (rc != HS_OK) return rc;
+            }
+            const double ms = std::chrono::duration<double, std::milli>(
+                                  std::chrono::steady_clock::now() - t0).count() / repeats;
+            if (ms < best_t) {
+                best_t = ms;
+                best = t;
+            }
+        }
+    store_tuned_shape(q, best);
+    if (best_ms) *best_ms = best_t;
     return HS_OK;
 }
 
@@ -376,7 +570,7 @@ hs_status hs_path_features(const hs_model* model, const double* corr, int64_t n_
     Pass pass;
     pass.scen = {0};
     pass.has_base_spot = true;
-    PassPlan pp = plan_pass(q, sh, sc, pass, default_target_waves());
+    PassPlan pp = plan_pass(q, sh, sc, pass, default_target_waves(), 0);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     unsigned char* ws = static_cast<unsigned char*>(d_workspace);
     const size_t off_groups = (pp.base.size() + 255) / 256 * 256;

@@ -235,7 +235,7 @@ hs_status validate(const Request& q)
         set_error("opts.waves_per_block = %d outside 0..%d", op.waves_per_block, kMaxWaves);
         return HS_EINVAL;
     }
-    if (op.flags & ~(HS_FLAG_EXPORT_TAU | HS_FLAG_TIMING)) {
+    if (op.flags & ~(HS_FLAG_EXPORT_TAU | HS_FLAG_TIMING | HS_FLAG_GRAPH)) {
         set_error("opts.flags = 0x%x has unknown bits", op.flags);
         return HS_EINVAL;
     }
@@ -504,7 +504,7 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
 }  // namespace
 
 PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,
-                   const Pass& pass, int target_waves)
+                   const Pass& pass, int target_waves, int wmax)
 {
     PassPlan pp;
     const int N = q.N;
@@ -545,8 +545,9 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
         cnt[best] += w;
     }
     for (auto& v : gs) std::sort(v.begin(), v.end());
+    const int wcap = std::max(1, std::min(wmax > 0 ? wmax : kMaxWaves, kMaxWaves));
     int W = q.opts.waves_per_block > 0 ? q.opts.waves_per_block
-                                       : std::min(static_cast<int>(gs.size()), kMaxWaves);
+                                       : std::min(static_cast<int>(gs.size()), wcap);
     W = std::max(W, wmin);
     W = std::min(W, kMaxWaves);
     pp.W = W;

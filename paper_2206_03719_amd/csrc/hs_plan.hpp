@@ -84,8 +84,9 @@ struct PassPlan {
     Layout lay;
 };
 
+// target_waves: waves the path kernel aims for; wmax: most waves per block.
 PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,
-                   const Pass& pass, int target_waves);
+                   const Pass& pass, int target_waves, int wmax);
 // Splits the Greek set into passes that each fit `workspace_bytes`
 // (one pass if everything fits).  Empty result = even one unit does not fit.
 std::vector<Pass> make_passes(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,

@@ -18,10 +18,20 @@ struct RunResult {
     int n_passes = 0;
 };
 
+// Launch shape of the path kernel (0 = default): the autotuner's output.
+struct Tune {
+    int target_waves = 0;
+    int wmax = 0;
+};
+
+// The tuned shape for requests like q (default if none was tuned).
+Tune tuned_shape(const Request& q);
+void store_tuned_shape(const Request& q, const Tune& t);
+
 // Enqueues and completes (synchronizes st) the whole Greek set of a validated
-// request in the given workspace; target_waves <= 0 = default.
+// request in the given workspace; tune == nullptr uses the tuned table.
 hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream_t st,
-                        RunResult& res, int target_waves);
+                        RunResult& res, const Tune* tune);
 void fill_greeks(const Request& q, const RunResult& res, hs_greeks* out);
 size_t workspace_bound(const Request& q, bool minimum);
 int default_target_waves();

@@ -137,7 +137,7 @@ void worker_main(hs_server* s)
         hs_status rc = HS_EDEVICE;
         std::string err;
         if (st) {
-            rc = run_greek_set(it->q, s->pool + off, it->ws, st, res, 0);
+            rc = run_greek_set(it->q, s->pool + off, it->ws, st, res, nullptr);
             if (rc != HS_OK) err = hs_last_error();
         } else {
             err = "could not create a HIP stream for this slot";
