@@ -3,16 +3,18 @@
 A step is one whole Greek set of the 5-asset Heston best-of American call
 (25,000 paths x 252 steps, 28 bump-and-revalue scenarios with common random
 numbers, FP32 paths / FP64 regression): path kernel, Gram kernel, backward
-sweep, results back on the host, Greeks.  Inputs are seeded and synthetic.
+sweep, results back on the host, Greeks.  Each pass of the set replays a
+cached HIP graph.  Inputs are seeded and synthetic and already in HBM; only
+the few-KB parameter tables go up and the scenario prices come back.
 
 Printed: one JSON line with the metric (Greek-set path-steps/s), the roofline
-of the dominant kernel (HIP-event times measured on the library's stream),
-the FP64 oracle timed on the host cores over a bounded sample, the accuracy
-of the timed results against the oracle, the plain per-scenario FP64 GPU
-comparator, and p50/p99 request latency of the serving loop under a Poisson
-stream of mixed-size requests.
+of the dominant kernel (HIP-event times on the library's stream), the FP64
+oracle timed on the host cores, the accuracy of the timed results against the
+oracle, the plain per-scenario FP64 GPU comparator, and p50/p99 request latency
+of the serving loop under a Poisson stream of mixed-size requests.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,6 +30,12 @@ import workloads as W  # noqa: E402
 
 METRIC = "Greek-set path-steps/s at <=1e-4 rel err vs FP64; p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
+# non-packed VALU lane-op slots per second: 256 CUs x 64 lanes x 2.4 GHz
+ALU_PEAK_OPS = 256 * 64 * 2.4e9
+KERNEL_SRC = os.path.join(ROOT, "paper_2206_03719_amd", "csrc", "hs_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "greekset_bestof5_25000x252_hbm_counters.txt")
+# device kernel names (prefixes) of the three stages
+KERNEL_NAMES = {"paths": "k_paths", "gram": "k_gram", "sweep": "k_sweep_cluster"}
 
 
 def log(msg):
@@ -62,6 +70,58 @@ def per_scenario_models(w):
     return out
 
 
+def path_kernel_slots(N, P, n, mask):
+    """Algorithmic VALU slots of the path kernel for one Greek set.
+
+    Per element (one path, step and asset): the random numbers cost about 70
+    slots (half a Philox4x32-10 call, ten rounds of two 32-bit multiply pairs
+    at quarter rate, plus one Box-Muller pair: log, sqrt, sin, cos) and are
+    paid once per base element, since every scenario reuses them; one
+    full-truncation Euler step with its correlation row costs 25 + (N+1)/2
+    slots (two sqrt and one exp at quarter rate, ~13 other operations) and is
+    paid for every element whose path differs from the base path: the base's
+    N assets, plus the assets at and after the bumped one for the v0 and
+    correlation scenarios and all N for the maturity and rate scenarios.
+    Spot scenarios rescale one asset of the base path: 4 slots each."""
+    own = N  # base
+    spot = 0
+    if mask & 1:
+        spot = 2 * N
+    if mask & 2:
+        own += N              # each v0 bump changes only its own asset
+    if mask & 4:
+        own += N              # maturity: a new time step for every asset
+    if mask & 8:
+        own += N              # rate: new drift for every asset
+    if mask & 16:
+        own += sum(N - j for j in range(1, N) for _ in range(j))  # rows j.. of L
+    per_path_step = 70 * N + (25 + (N + 1) / 2) * own + 4 * spot
+    return per_path_step * P * n
+
+
+def read_counters(path):
+    """HBM bytes per dispatch from the committed counter summary, or None when
+    it is missing or was taken on another version of the kernel source."""
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    fields = dict(l.split(":", 1) for l in lines if ":" in l and not l.startswith(("#", " ")))
+    if fields.get("kernel_source_sha256", "").strip() != src:
+        return None
+    ff = float(fields["fetch_scale"])
+    wf = float(fields["write_scale"])
+    out = {}
+    for l in lines:
+        if l.startswith("traffic "):
+            # traffic <stage> fetch_kib=<x> write_kib=<y>
+            parts = l.split()
+            kv = dict(p.split("=") for p in parts[2:])
+            out[parts[1]] = (float(kv["fetch_kib"]) * ff + float(kv["write_kib"]) * wf) * 1024.0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,8 +130,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -83,23 +147,36 @@ def main():
 
     hs.lib()
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 1 GiB 5 times")
+        return
     w = W.best_of_call(n_assets=5, n_paths=25000, n_steps=252, precision="fp32")
     N, P, n = 5, w["n_paths"], w["n_steps"]
     S = hs.num_scenarios(N, w["bumps"]["mask"])
     nbytes = hs.workspace_bytes(w["model"], w["option"], P, n, w["bumps"], "fp32")
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # a non-null stream: graph replay needs one
+    graph = not args.no_graph
 
     def step(timing=False):
         return hs.price_greeks(w["model"], w["corr"], w["option"], P, n, w["bumps"],
                                seed=w["seed"], precision="fp32", workspace=ws, stream=stream,
-                               timing=timing)
+                               timing=timing, graph=graph and not timing)
 
+    if args.autotune:
+        best = hs.autotune(w["model"], w["corr"], w["option"], P, n, w["bumps"], seed=w["seed"],
+                           workspace=ws, stream=stream, repeats=3)
+        log("autotuned: %.3f ms per Greek set" % best)
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
         res = step()
     torch.cuda.synchronize()
-    log("timing %d Greek sets" % args.steps)
+    log("timing %d Greek sets%s" % (args.steps, " (graph replay)" if graph else ""))
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res = step()
@@ -110,34 +187,59 @@ def main():
     value = path_steps / (ms * 1e-3)
     log("%.3f ms per Greek set, %.3e path-steps/s" % (ms, value))
 
-    # per-kernel device times (HIP events on the library's stream)
+    # per-kernel device times: the same K Greek sets launched eagerly with HIP
+    # events around each stage on the library's stream
     kt = {"paths": [], "gram": [], "sweep": []}
-    for _ in range(5):
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
         r = step(timing=True)
         kt["paths"].append(r["t_paths_ms"])
         kt["gram"].append(r["t_gram_ms"])
         kt["sweep"].append(r["t_sweep_ms"])
-    kms = {k: float(np.median(v)) for k, v in kt.items()}
-    log("kernel ms (median of 5): %s" % json.dumps(kms))
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
+    kms = {k: float(np.mean(v)) for k, v in kt.items()}
+    log("kernel ms (mean of %d): %s; eager set %.3f ms" % (args.steps, json.dumps(kms), ms_eager))
     # algorithmic bytes per launch: features are 8 B (FP32 U, A) per path-step;
     # the path kernel writes them once, the Gram kernel reads dates 1..n-1,
     # the sweep reads every date once
     alg = {"paths": S * P * n * 8.0, "gram": S * P * (n - 1) * 8.0, "sweep": S * P * n * 8.0}
+    slots = path_kernel_slots(N, P, n, w["bumps"]["mask"])
+    traffic = read_counters(COUNTERS)
+    per_kernel = {}
+    for k in kms:
+        sec = kms[k] * 1e-3
+        per_kernel[k] = {"kernel": KERNEL_NAMES[k], "ms": round(kms[k], 4),
+                         "alg_bytes": alg[k], "hbm_GBs": round(alg[k] / sec / 1e9, 1),
+                         "hbm_frac": round(alg[k] / sec / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic_bytes": traffic.get(k) if traffic else None}
+    per_kernel["paths"]["alu_slots"] = slots
+    per_kernel["paths"]["alu_frac"] = round(slots / (kms["paths"] * 1e-3) / ALU_PEAK_OPS, 4)
     dom = max(kms, key=kms.get)
-    achieved = alg[dom] / (kms[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "kernel_ms": kms,
-                "per_kernel_GBs": {k: round(alg[k] / (kms[k] * 1e-3) / 1e9, 1) for k in kms}}
+    sec = kms[dom] * 1e-3
+    if dom == "paths":
+        # the path kernel is bound by VALU and transcendental issue, not HBM
+        roofline = {"bound": "alu", "kernel": KERNEL_NAMES[dom],
+                    "achieved": round(slots / sec / 1e12, 3), "peak": ALU_PEAK_OPS / 1e12,
+                    "unit": "Tslot/s", "frac": round(slots / sec / ALU_PEAK_OPS, 4)}
+    else:
+        achieved = alg[dom] / sec / 1e9
+        roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roofline["traffic"] = traffic.get(dom) if traffic else None
+    roofline["kernel_ms"] = round(kms[dom], 4)
+    roofline["per_kernel"] = per_kernel
 
     out = {"metric": METRIC, "value": value, "unit": "path-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32 paths / f64 regression", "data": "synthetic",
+           "dtype": "f32", "data": "synthetic",
            "config": {"workload": "heston-bestof-call-5x25000x252 greek set (28 scenarios)",
                       "n_assets": N, "n_paths": P, "n_steps": n, "n_scenarios": S,
-                      "precision": "fp32 paths, fp64 regression", "seed": w["seed"],
-                      "elements_per_s": value * N},
+                      "precision": "f32 paths, f64 regression", "seed": w["seed"],
+                      "graph": graph, "elements_per_s": value * N,
+                      "eager_ms_per_step": ms_eager},
            "roofline": roofline}
 
     if not args.no_cpu_baseline:
@@ -150,8 +252,10 @@ def main():
         t1 = time.perf_counter()
         out["cpu_baseline"] = {"value": path_steps / (t1 - t0), "unit": "path-steps/s",
                                "cores": threads, "kind": "oracle",
-                               "sample": "the full 28-scenario Greek set (25k x 252), FP64",
-                               "seconds": t1 - t0}
+                               "sample": "the whole 28-scenario Greek set (25k paths x 252 "
+                                         "steps, FP64): the regression couples all paths",
+                               "seconds": t1 - t0, "cpu": cpu_model(),
+                               "host_cpus": os.cpu_count()}
         err = np.abs(res["scenario_price"] - o["scenario_price"]) / np.abs(o["scenario_price"])
         acc = {"max_price_rel_err": float(err.max()),
                "delta_max_rel_err": float(np.max(np.abs(res["delta"] - o["delta"]) /
@@ -188,6 +292,16 @@ def main():
         log("serving: %s" % json.dumps(out["latency"]))
 
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    try:
+        for l in open("/proc/cpuinfo"):
+            if l.startswith("model name"):
+                return l.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def serve_leg(hs, torch, n_req):
