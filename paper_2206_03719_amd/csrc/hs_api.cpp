@@ -336,7 +336,8 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         if (L.cluster) {
             L.cluster_q = sh.cluster_q;
             L.per_launch = std::max(1, cap / sh.cluster_g);
-            L.part_count = static_cast<int64_t>(Sp) * (q.n + 2) * sh.cluster_g * kPartStride;
+            L.part_count = static_cast<int64_t>(Sp) * cluster_rows(sh.american, q.n) *
+                           sh.cluster_g * kPartStride;
             L.ca.partials = reinterpret_cast<double*>(ws + pp.lay.part);
             L.ca.error = L.err_flag;
             L.ca.G = sh.cluster_g;

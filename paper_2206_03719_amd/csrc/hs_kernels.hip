@@ -75,15 +75,19 @@ __device__ __forceinline__ double unit_f64(uint32_t w)
     return static_cast<double>(2u * (w >> 9) + 1u) * 0x1p-24;
 }
 
-// Box-Muller: R = sqrt(-2 ln u1), (eps, eta) = R (cos 2 pi u2, sin 2 pi u2);
-// sincospi takes 2 u2 exactly, so no rounding of the angle.
+// Box-Muller: R = sqrt(-2 ln u1), (eps, eta) = R (cos 2 pi u2, sin 2 pi u2).
+// FP32 uses the hardware transcendentals: v_log_f32 is log2 (so -2 ln u =
+// -2 ln 2 log2 u), and v_sin_f32 / v_cos_f32 take their argument in turns, so
+// u2 goes in exactly with no 2 pi rounding.  Each is good to a few ulp, far
+// inside the FP32 path's error budget, at a fraction of the library calls'
+// instruction count.  FP64 keeps the correctly rounded library functions
+// (sincospi takes 2 u2 exactly).
 __device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, float& e, float& h)
 {
-    const float R = sqrtf(-2.0f * logf(unit_f32(w1)));
-    float s, c;
-    sincospif(2.0f * unit_f32(w2), &s, &c);
-    e = R * c;
-    h = R * s;
+    const float R = __builtin_amdgcn_sqrtf(-1.38629436112f * __builtin_amdgcn_logf(unit_f32(w1)));
+    const float u2 = unit_f32(w2);
+    e = R * __builtin_amdgcn_cosf(u2);
+    h = R * __builtin_amdgcn_sinf(u2);
 }
 __device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, double& e, double& h)
 {
@@ -94,9 +98,11 @@ __device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, double& e, 
     h = R * s;
 }
 
-__device__ __forceinline__ float exp_r(float x) { return expf(x); }
+// FP32: e^x = 2^(x log2 e) on v_exp_f32, and v_sqrt_f32 (arguments here are
+// >= 0 and far from overflow); FP64: the library functions.
+__device__ __forceinline__ float exp_r(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504089f); }
 __device__ __forceinline__ double exp_r(double x) { return exp(x); }
-__device__ __forceinline__ float sqrt_r(float x) { return sqrtf(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 
 template <typename R>
@@ -488,21 +494,38 @@ __device__ __forceinline__ void gram_finish(int m, const double (&g)[15], double
 }
 
 // ---------------------------------------------------------------------------
-// Gram kernel: block (date k = blockIdx.x + 1, scenario blockIdx.y).
+// Gram kernel: block (date k = blockIdx.x + 1, scenario blockIdx.y), one pass
+// over the date's features.  Over the in-the-money paths it sums the moments
+// S_ab = sum y^a z^b of the fixed-shift variables y = (U - K)/K and
+// z = A/tbar - 1 (12 monomials: a <= 4, b <= 2, those the basis products
+// need), then shifts them to the regression-set means, d = S_10/S_00 and
+// e = S_01/S_00: M_ij = sum (y - d)^i (z - e)^j by the binomial expansion.
+// x = y - d and w = z - e are the centred basis variables, so the Gram matrix
+// entry of phi_p phi_q is M at the summed exponents.  The shift is small
+// against the spread of y and z, so the expansion loses little precision.
+
+// monomial (a, b) -> slot in the moment array
+__device__ __host__ constexpr int mono(int a, int b)
+{
+    return b == 0 ? a : (b == 1 ? 5 + a : 9 + a);  // (0..4,0) (0..3,1) (0..2,2)
+}
 
 template <typename R>
 __global__ void __launch_bounds__(kGramThreads) k_gram(const LsmcArgs A)
 {
-    constexpr int U1 = 8, U2 = 4;  // loads in flight per thread in the two passes
-    __shared__ double red[(kGramThreads / 64 + 1) * 15];
+    constexpr int U1 = 8;  // loads in flight per thread
+    __shared__ double red[(kGramThreads / 64 + 1) * 12];
     const int s = blockIdx.y;
     const int k = blockIdx.x + 1;
     const R2<R>* __restrict__ F =
         static_cast<const R2<R>*>(A.feat) + s * A.plane + static_cast<int64_t>(k - 1) * A.P;
     const int nw = kGramThreads / 64;
     const int64_t P = A.P;
+    const bool two = A.m == 5;  // the basis has w terms
 
-    double c3[3] = {0.0, 0.0, 0.0};
+    double S[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) S[i] = 0.0;
     for (int64_t p0 = threadIdx.x; p0 < P; p0 += kGramThreads * U1) {
         R2<R> f[U1];
 #pragma unroll
@@ -517,58 +540,71 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const LsmcArgs A)
         }
 #pragma unroll
         for (int u = 0; u < U1; ++u) {
-            const double U = static_cast<double>(f[u].u);
-            if (p0 + u * kGramThreads < P && payoff(A.cp, A.K, U) > 0.0) {
-                c3[0] += 1.0;
-                c3[1] += U;
-                c3[2] += static_cast<double>(f[u].a);
+            const double Uv = static_cast<double>(f[u].u);
+            if (p0 + u * kGramThreads < P && payoff(A.cp, A.K, Uv) > 0.0) {
+                const double y = (Uv - A.K) * A.inv_K;
+                const double y2 = y * y;
+                const double y3 = y2 * y;
+                S[mono(0, 0)] += 1.0;
+                S[mono(1, 0)] += y;
+                S[mono(2, 0)] += y2;
+                S[mono(3, 0)] += y3;
+                S[mono(4, 0)] += y2 * y2;
+                if (two) {
+                    const double z = static_cast<double>(f[u].a) * A.inv_tbar - 1.0;
+                    const double z2 = z * z;
+                    S[mono(0, 1)] += z;
+                    S[mono(1, 1)] += y * z;
+                    S[mono(2, 1)] += y2 * z;
+                    S[mono(3, 1)] += y3 * z;
+                    S[mono(0, 2)] += z2;
+                    S[mono(1, 2)] += y * z2;
+                    S[mono(2, 2)] += y2 * z2;
+                }
             }
         }
     }
-    block_sum<3>(c3, red, nw);
+    block_sum<12>(S, red, nw);
+    if (threadIdx.x != 0) return;
     RegRec* rr = A.reg + static_cast<int64_t>(s) * A.n + (k - 1);
-    const double cnt = c3[0];
-    if (cnt < static_cast<double>(A.m)) {
-        if (threadIdx.x == 0) {
-            rr->ok = 0.0;
-            rr->cnt = cnt;
-        }
+    const double cnt = S[mono(0, 0)];
+    const int m = A.m;
+    if (cnt < static_cast<double>(m)) {
+        rr->ok = 0.0;
+        rr->cnt = cnt;
         return;
     }
-    const double cU = c3[1] / cnt;
-    const double cA = c3[2] / cnt;
-    const int m = A.m;
+    const double d = S[mono(1, 0)] / cnt;
+    const double e = two ? S[mono(0, 1)] / cnt : 0.0;
+    // powers of -d and -e, binomial coefficients up to 4
+    double nd[5], ne[3];
+    nd[0] = 1.0;
+    ne[0] = 1.0;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) nd[i] = nd[i - 1] * -d;
+    ne[1] = -e;
+    ne[2] = e * e;
+    constexpr double binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0},
+                                    {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+    // centred moment M_ij from the fixed-shift sums
+    auto M = [&](int i, int j) {
+        double acc = 0.0;
+        for (int b = 0; b <= j; ++b)
+            for (int a = 0; a <= i; ++a)
+                acc += binom[i][a] * binom[j][b] * nd[i - a] * ne[j - b] * S[mono(a, b)];
+        return acc;
+    };
+    // basis exponents: phi = {1, x, x^2, w, x w}
+    constexpr int ex[5] = {0, 1, 2, 0, 1};
+    constexpr int ew[5] = {0, 0, 0, 1, 1};
     double g[15];
+    int idx = 0;
 #pragma unroll
-    for (int i = 0; i < 15; ++i) g[i] = 0.0;
-    for (int64_t p0 = threadIdx.x; p0 < P; p0 += kGramThreads * U2) {
-        R2<R> f[U2];
+    for (int a = 0; a < 5; ++a)
 #pragma unroll
-        for (int u = 0; u < U2; ++u) {
-            const int64_t p = p0 + u * kGramThreads;
-            if (p < P) {
-                f[u] = F[p];
-            } else {
-                f[u].u = R(0);
-                f[u].a = R(0);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U2; ++u) {
-            const double U = static_cast<double>(f[u].u);
-            if (p0 + u * kGramThreads < P && payoff(A.cp, A.K, U) > 0.0) {
-                double phi[5];
-                basis(m, U, static_cast<double>(f[u].a), cU, cA, A.inv_K, A.inv_tbar, phi);
-                int idx = 0;
-#pragma unroll
-                for (int a = 0; a < 5; ++a)
-#pragma unroll
-                    for (int b = 0; b <= a; ++b, ++idx) g[idx] += phi[a] * phi[b];
-            }
-        }
-    }
-    block_sum<15>(g, red, nw);
-    if (threadIdx.x == 0) gram_finish(m, g, cU, cA, cnt, rr);
+        for (int b = 0; b <= a; ++b, ++idx)
+            g[idx] = (a < m && b < m) ? M(ex[a] + ex[b], ew[a] + ew[b]) : 0.0;
+    gram_finish(m, g, A.K + A.K * d, (1.0 + e) / A.inv_tbar, cnt, rr);
 }
 
 // ---------------------------------------------------------------------------
@@ -767,63 +803,89 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// Cluster sweep: G workgroups per scenario, each holding 256 Q paths' cash
-// flow, exercise date and two dates of features in registers.  Once per
-// exercise date the workgroups of a scenario exchange their right-hand-side
-// partials through per-date slots in the workspace: each slot starts empty
-// (kEmptySlot) and receives exactly one 64-bit value, so a reader that sees a
-// non-empty slot has the value itself -- no counter, no fence.  Every
-// workgroup folds the G partials in workgroup order (the same sum everywhere)
-// and solves for the regression coefficients itself.  A wait longer than
+// Cluster sweep: G workgroups per scenario, each holding 512 Q paths' cash
+// flow, exercise date and three dates of features in registers.  Once per
+// exercise date each wave reduces its right-hand-side partials (a fixed DPP
+// tree over its 64 lanes) into LDS; after a barrier, wave q folds component q
+// over the waves in order and publishes the workgroup's partial into its slot
+// of a per-date row in the workspace.  A slot starts empty (kEmptySlot) and
+// receives exactly one 64-bit value, so a reader that sees a non-empty slot
+// has the value itself -- no counter, no fence.  Wave q then folds component q
+// of the G workgroup partials in one fixed order (lane l takes slots l,
+// l + 64, ... in turn, then a DPP tree over the lanes), so all workgroups hold
+// the same sum; a second barrier hands it to the other waves, and each thread
+// solves for the regression coefficients itself.  A wait longer than
 // timeout_ticks of the wall clock sets the error flag and all workgroups
 // leave the kernel.
 
-// v: this workgroup's reduced partial (same in every thread).  On return v
-// holds the scenario total; false if a wait timed out.
+// LDS of the cluster sweep, after the discount table: wave partials [2][NW][8]
+// (G == 1), totals [2][8], status flag.
+struct ClusterLds {
+    double* part;
+    double* tot;
+    int* flag;
+};
+
+// b: this thread's partials.  On return b holds the scenario totals (every
+// thread); false if a wait timed out.  par alternates between consecutive
+// calls so that no wave overwrites totals another wave has not read yet.
 template <int K>
-__device__ __forceinline__ bool cluster_sum(double (&v)[K], int m, double* row, int G, int g,
-                                            const ClusterArgs& C, double* gat, int* flag)
+__device__ __forceinline__ bool cluster_exchange(double (&b)[K], int m, double* row, int G, int g,
+                                                 int par, const ClusterArgs& C, const ClusterLds& L)
 {
-    if (G == 1) return true;
-    if (threadIdx.x == 0) {
+    constexpr int NW = kClusterThreads / 64;
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+    for (int q = 0; q < K; ++q) b[q] = wave_sum_lane63(b[q]);
+    if (lane == 63) {
 #pragma unroll
         for (int q = 0; q < K; ++q)
-            if (q < m)
+            if (q < m) L.part[(par * NW + wid) * kPartStride + q] = b[q];
+    }
+    __syncthreads();
+    if (wid < m) {
+        const int q = wid;
+        double t = L.part[(par * NW) * kPartStride + q];
+        for (int w = 1; w < NW; ++w) t += L.part[(par * NW + w) * kPartStride + q];
+        if (G == 1) {
+            if (lane == 0) L.tot[par * kPartStride + q] = t;
+        } else {
+            if (lane == 0)
                 __hip_atomic_store(reinterpret_cast<uint64_t*>(row + g * kPartStride + q),
-                                   __builtin_bit_cast(uint64_t, v[q]), __ATOMIC_RELAXED,
+                                   __builtin_bit_cast(uint64_t, t), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-    }
-    for (int i = threadIdx.x; i < G * m; i += kClusterThreads) {
-        const int gg = i / m, q = i - gg * m;
-        uint64_t* slot = reinterpret_cast<uint64_t*>(row + gg * kPartStride + q);
-        uint64_t x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (x == kEmptySlot) {
-            const long long t0 = wall_clock64();
-            for (;;) {
-                __builtin_amdgcn_s_sleep(2);
-                x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (x != kEmptySlot) break;
-                if (__hip_atomic_load(C.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                    wall_clock64() - t0 > C.timeout_ticks) {
-                    __hip_atomic_store(C.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    *flag = 0;
-                    break;
+            double acc = 0.0;
+            bool bad = false;
+            for (int j = lane; j < G; j += 64) {
+                uint64_t* slot = reinterpret_cast<uint64_t*>(row + j * kPartStride + q);
+                uint64_t x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (x == kEmptySlot) {
+                    const long long t0 = wall_clock64();
+                    for (;;) {
+                        __builtin_amdgcn_s_sleep(1);
+                        x = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (x != kEmptySlot) break;
+                        if (__hip_atomic_load(C.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                            wall_clock64() - t0 > C.timeout_ticks) {
+                            __hip_atomic_store(C.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            bad = true;
+                            break;
+                        }
+                    }
                 }
+                if (bad) break;
+                acc += __builtin_bit_cast(double, x);
             }
+            if (bad) *L.flag = 0;
+            acc = wave_sum_lane63(acc);
+            if (lane == 63) L.tot[par * kPartStride + q] = acc;
         }
-        gat[gg * K + q] = __builtin_bit_cast(double, x);
     }
     __syncthreads();
-    if (*flag == 0) return false;
-    if (threadIdx.x < m) {
-        double acc = gat[threadIdx.x];
-        for (int gg = 1; gg < G; ++gg) acc += gat[gg * K + threadIdx.x];
-        gat[G * K + threadIdx.x] = acc;
-    }
-    __syncthreads();
+    if (*L.flag == 0) return false;
 #pragma unroll
-    for (int q = 0; q < K; ++q) v[q] = q < m ? gat[G * K + q] : 0.0;
-    __syncthreads();
+    for (int q = 0; q < K; ++q) b[q] = q < m ? L.tot[par * kPartStride + q] : 0.0;
     return true;
 }
 
@@ -836,9 +898,10 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     const int n = A.n;
     const int G = C.G;
     double* const sdisc = reinterpret_cast<double*>(hs_smem);  // [n+1]
-    double* const red = sdisc + ((n + 2) & ~1);                 // [NW + 1][5]
-    double* const gat = red + (NW + 1) * 5;                     // [G+1][5]
-    int* const flag = reinterpret_cast<int*>(gat + (G + 1) * 5);
+    ClusterLds Ls;
+    Ls.part = sdisc + ((n + 2) & ~1);                          // [2][NW][8]
+    Ls.tot = Ls.part + 2 * NW * kPartStride;                   // [2][8]
+    Ls.flag = reinterpret_cast<int*>(Ls.tot + 2 * kPartStride);
     const int sl = blockIdx.x / G;
     const int g = blockIdx.x - sl * G;
     const int s = C.s0 + sl;
@@ -847,20 +910,29 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     const R2<R>* __restrict__ F = static_cast<const R2<R>*>(A.feat) + s * A.plane;
     for (int j = threadIdx.x; j <= n; j += kClusterThreads)
         sdisc[j] = A.disc[static_cast<int64_t>(s) * (n + 1) + j];
-    if (threadIdx.x == 0) *flag = 1;
+    if (threadIdx.x == 0) *Ls.flag = 1;
     __syncthreads();
 
-    double* const part = C.partials + static_cast<int64_t>(s) * (n + 2) * G * kPartStride;
+    const int64_t row_len = static_cast<int64_t>(G) * kPartStride;
+    const bool amer = A.american != 0;
+    double* const part = C.partials +
+                         (static_cast<int64_t>(s) * cluster_rows(amer, n) - cluster_row0(amer, n)) *
+                             row_len;
     const cptr<RegRec> recs = as_const<RegRec>(A.reg) + static_cast<int64_t>(s) * n;
     const int64_t pbase = static_cast<int64_t>(g) * (kClusterThreads * Q) + threadIdx.x;
     const int64_t last = A.american ? static_cast<int64_t>(n - 1) * P : 0;
+    int par = 0;
 
+    // path pbase + i kClusterThreads exists iff i < nlive (the last workgroup
+    // of a scenario may be ragged)
+    const int64_t room = P - pbase;
+    const int nlive = room <= 0 ? 0 : (room + kClusterThreads - 1) / kClusterThreads;
     double cf[Q];
     int tau[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int64_t p = pbase + i * kClusterThreads;
-        cf[i] = p < P ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) : 0.0;
+        cf[i] = i < nlive ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) : 0.0;
         tau[i] = n;
     }
 
@@ -868,37 +940,32 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     double bcU = 0.0, bcA = 0.0;
     bool have = false;  // beta of the later date k+1 is valid
     double skipped = 0.0;
-    // pu/pa: features of date k+1 (its exercise decision); cu/ca: date k (this
-    // iteration's regression); nu/na: date k-1, loaded one iteration ago; the
-    // loads of date k-2 are issued during this iteration's exchange.
-    R cu[Q], ca[Q], pu[Q], pa[Q], nu[Q], na[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        pu[i] = R(0);
-        pa[i] = R(0);
-        cu[i] = R(0);
-        ca[i] = R(0);
-        nu[i] = R(0);
-        na[i] = R(0);
-    }
     if (A.american) {
+        // pu/pa: features of date k+1 (its exercise decision); cu/ca: date k
+        // (this iteration's regression); nu/na: date k-1, loaded one iteration
+        // ago; the loads of date k-2 are issued during this iteration's exchange.
+        R cu[Q], ca[Q], pu[Q], pa[Q], nu[Q], na[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int64_t p = pbase + i * kClusterThreads;
-            if (p < P && n >= 2) {
+            pu[i] = R(0);
+            pa[i] = R(0);
+            cu[i] = R(0);
+            ca[i] = R(0);
+            nu[i] = R(0);
+            na[i] = R(0);
+            if (i < nlive && n >= 2) {
                 const R2<R> f = F[static_cast<int64_t>(n - 2) * P + p];
                 cu[i] = f.u;
                 ca[i] = f.a;
             }
-            if (p < P && n >= 3) {
+            if (i < nlive && n >= 3) {
                 const R2<R> f = F[static_cast<int64_t>(n - 3) * P + p];
                 nu[i] = f.u;
                 na[i] = f.a;
             }
         }
-    }
-    if (A.american) {
-        // regression record of date k, loaded one date ahead
+        // regression-set flag and means of date k, loaded one date ahead
         double r_ok = n >= 2 ? recs[n - 2].ok : 0.0;
         double r_cU = n >= 2 ? recs[n - 2].cU : 0.0;
         double r_cA = n >= 2 ? recs[n - 2].cA : 0.0;
@@ -910,13 +977,15 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
                 r_cU = recs[k - 2].cU;
                 r_cA = recs[k - 2].cA;
             }
-            // exercise at date k+1 with its regression
-            if (have) {
+            // per path: exercise at date k+1 with its regression, then this
+            // date's right-hand side with the updated cash flow
+            double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int i = 0; i < Q; ++i) {
+            for (int i = 0; i < Q; ++i) {
+                if (have) {
                     const double U = static_cast<double>(pu[i]);
                     const double h = payoff(A.cp, A.K, U);
-                    if (pbase + i * kClusterThreads < P && h > 0.0) {
+                    if (i < nlive && h > 0.0) {
                         double phi[5];
                         basis(m, U, static_cast<double>(pa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
                         double cont = 0.0;
@@ -928,14 +997,9 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
                         }
                     }
                 }
-            }
-            const cptr<RegRec> rr = recs + (k - 1);
-            double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            if (ok) {
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
+                if (ok) {
                     const double U = static_cast<double>(cu[i]);
-                    if (pbase + i * kClusterThreads < P && payoff(A.cp, A.K, U) > 0.0) {
+                    if (i < nlive && payoff(A.cp, A.K, U) > 0.0) {
                         double phi[5];
                         basis(m, U, static_cast<double>(ca[i]), cU, cA, A.inv_K, A.inv_tbar, phi);
                         const double Y = cf[i] * sdisc[tau[i] - k];
@@ -944,36 +1008,37 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
                             if (q < m) b[q] += phi[q] * Y;
                     }
                 }
-                block_sum<5>(b, red, NW);
-            }
-            // date k+1 is decided: its registers take date k-2, loaded while
-            // the scenario's workgroups meet
-            if (k > 2) {
-                const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 3) * P;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const int64_t p = pbase + i * kClusterThreads;
-                    if (p < P) {
-                        const R2<R> f = Fn[p];
-                        pu[i] = f.u;
-                        pa[i] = f.a;
-                    }
-                }
             }
             if (ok) {
-                if (!cluster_sum<5>(b, m, part + static_cast<int64_t>(k) * G * kPartStride, G, g,
-                                    C, gat, flag))
-                    return;
-                double L[15];
+                // the inverse factor's loads fly during the exchange
+                double Lk[15];
 #pragma unroll
-                for (int i = 0; i < 15; ++i) L[i] = rr->L[i];
-                solve_packed(m, L, b, beta);
+                for (int i = 0; i < 15; ++i) Lk[i] = recs[k - 1].L[i];
+                if (!cluster_exchange<5>(b, m, part + static_cast<int64_t>(k) * row_len, G, g, par,
+                                         C, Ls))
+                    return;
+                par ^= 1;
+                solve_packed(m, Lk, b, beta);
                 bcU = cU;
                 bcA = cA;
                 have = true;
             } else {
                 skipped += 1.0;
                 have = false;
+            }
+            // date k+1 is decided: its registers take date k-2, used two
+            // iterations on.  Issued after the exchange, whose slot polls would
+            // otherwise wait for these loads (vector loads complete in order).
+            if (k > 2) {
+                const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 3) * P;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if (i < nlive) {
+                        const R2<R> f = Fn[pbase + i * kClusterThreads];
+                        pu[i] = f.u;
+                        pa[i] = f.a;
+                    }
+                }
             }
             // rotate: k becomes the decision date, k-1 the regression date, and
             // the k-2 loads the next prefetched date
@@ -993,7 +1058,7 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
             for (int i = 0; i < Q; ++i) {
                 const double U = static_cast<double>(pu[i]);
                 const double h = payoff(A.cp, A.K, U);
-                if (pbase + i * kClusterThreads < P && h > 0.0) {
+                if (i < nlive && h > 0.0) {
                     double phi[5];
                     basis(m, U, static_cast<double>(pa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
                     double cont = 0.0;
@@ -1011,28 +1076,24 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     // price and standard error over the whole scenario
     double s1[1] = {0.0};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int64_t p = pbase + i * kClusterThreads;
-        if (p < P) s1[0] += cf[i] * sdisc[tau[i]];
-    }
-    block_sum<1>(s1, red, NW);
-    if (!cluster_sum<1>(s1, 1, part + static_cast<int64_t>(n) * G * kPartStride, G, g, C, gat,
-                        flag))
+    for (int i = 0; i < Q; ++i)
+        if (i < nlive) s1[0] += cf[i] * sdisc[tau[i]];
+    if (!cluster_exchange<1>(s1, 1, part + static_cast<int64_t>(n) * row_len, G, g, par, C, Ls))
         return;
+    par ^= 1;
     const double mean = s1[0] / static_cast<double>(P);
     double s2[1] = {0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int64_t p = pbase + i * kClusterThreads;
-        if (p < P) {
+        if (i < nlive) {
             const double d = cf[i] * sdisc[tau[i]] - mean;
             s2[0] += d * d;
             if (A.export_tau) A.tau[static_cast<int64_t>(s) * P + p] = tau[i];
         }
     }
-    block_sum<1>(s2, red, NW);
-    if (!cluster_sum<1>(s2, 1, part + static_cast<int64_t>(n + 1) * G * kPartStride, G, g, C,
-                        gat, flag))
+    if (!cluster_exchange<1>(s2, 1, part + static_cast<int64_t>(n + 1) * row_len, G, g, par, C,
+                             Ls))
         return;
     if (g == 0 && threadIdx.x == 0) {
         double* o = A.out + static_cast<int64_t>(s) * 4;
@@ -1191,7 +1252,9 @@ int cluster_capacity_t(size_t lds)
 
 size_t cluster_lds_bytes(int n, int G)
 {
-    return sizeof(double) * (((n + 2) & ~1) + (kClusterThreads / 64 + 1) * 5 + (G + 1) * 5) + 16;
+    (void)G;
+    return sizeof(double) * (((n + 2) & ~1) + 2 * (kClusterThreads / 64) * kPartStride +
+                             2 * kPartStride) + 16;
 }
 
 int cluster_capacity(bool fp32, int q, size_t lds)

@@ -88,17 +88,23 @@ struct LsmcArgs {
 };
 
 // Cluster sweep: G workgroups of kClusterThreads cooperate on one scenario,
-// meeting once per exercise date at a per-scenario counter.
+// meeting once per exercise date through per-workgroup partial slots.
 constexpr int kClusterThreads = 512;
-constexpr int kPartStride = 8;  // doubles per published partial
+constexpr int kPartStride = 8;  // doubles per published workgroup partial
 constexpr int kMaxClusterGroups = 1024;
 
 // Partial slots start as kEmptySlot (a NaN bit pattern that arithmetic never
 // produces); a workgroup's published partial is the slot's only write.
 constexpr uint64_t kEmptySlot = ~0ull;
 
+// Exchange rows of a scenario: one per exercise date k = 1..n-1 (American
+// only) and two for the price sums (rows n and n + 1); row0 is the first
+// stored row (0 for American, n for European).
+constexpr int cluster_row0(bool american, int n) { return american ? 0 : n; }
+constexpr int cluster_rows(bool american, int n) { return n + 2 - cluster_row0(american, n); }
+
 struct ClusterArgs {
-    double* partials;     // [scen][n + 2][G][kPartStride], filled with kEmptySlot
+    double* partials;     // [scen][rows][G][kPartStride], filled with kEmptySlot
     int32_t* error;       // set to 1 if a wait timed out
     int32_t s0;           // first scenario (plane) of this launch
     int32_t G;            // workgroups per scenario

@@ -414,8 +414,8 @@ Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, in
     off = align_up(off + (S + 64) * sizeof(uint32_t));
     L.part = off;
     if (sh.sweep == kSweepCluster)  // rows: dates 1..n-1, then the two price sums
-        off = align_up(off + S * (q.n + 2) * static_cast<size_t>(sh.cluster_g) * kPartStride *
-                                 sizeof(double));
+        off = align_up(off + S * cluster_rows(sh.american, q.n) *
+                                 static_cast<size_t>(sh.cluster_g) * kPartStride * sizeof(double));
     L.feat = off;
     off = align_up(off + S * nd * P * 2 * R);
     L.total = off;

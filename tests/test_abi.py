@@ -46,7 +46,9 @@ def test_workspace_sizes():
     full = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"])
     mn = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"], minimum=True)
     feat = 28 * 252 * 25000 * 8
-    assert feat <= full < feat * 1.02
+    # features plus a few percent: regression records, cash flows, exercise
+    # dates and the per-wave exchange slots of the cluster sweep
+    assert feat <= full < feat * 1.04
     assert mn < full
     f64 = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"], precision="fp64")
     assert f64 > 1.9 * feat
