@@ -56,7 +56,9 @@ double mean_theta(const Request& q)
 
 }  // namespace
 
-int default_target_waves() { return 2048; }
+// about three waves per SIMD when paths are few; fewer waves per block (less
+// per-wave feature work) once the paths alone fill the device
+int default_target_waves() { return 3072; }
 
 // ---------------------------------------------------------------------------
 // Tuning table: launch shape of the path kernel per request class.
