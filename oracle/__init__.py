@@ -54,6 +54,10 @@ def lib(path=None):
         L.orc_features.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, dp]
         L.orc_features.restype = ctypes.c_int
+        L.orc_features_at.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_uint64, dp]
+        L.orc_features_at.restype = ctypes.c_int
         L.orc_lsmc.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_double, ctypes.c_int32, dp,
@@ -187,6 +191,22 @@ def features(model, corr, T, n_steps, n_paths, seed, nthreads=0):
                             int(seed), int(nthreads), _dp(out))
     if st != OK:
         raise ValueError("orc_features failed with status %d" % st)
+    return out
+
+
+def features_at(model, corr, T, n_steps, paths, seed):
+    """(len(paths), n_steps, 2) array of (U, A) at dates 1..n for the given path
+    indices of one scenario (the same paths as features() produces)."""
+    keep = []
+    m = _model_struct(model, keep)
+    C = _f64(corr)
+    idx = np.ascontiguousarray(np.asarray(paths, dtype=np.int64))
+    out = np.empty((len(idx), n_steps, 2))
+    st = lib().orc_features_at(ctypes.byref(m), _dp(C), float(T), int(n_steps), len(idx),
+                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(seed),
+                               _dp(out))
+    if st != OK:
+        raise ValueError("orc_features_at failed with status %d" % st)
     return out
 
 

@@ -179,6 +179,44 @@ typedef struct {
  * Reduction at each date k = 1..n (Sec. 4.1): U = max_i S_i (U = S for one
  * asset) and A = (1/N) sum_i max(v_i, 0).
  * Output feat[((k-1) P + p) * 2 + {0,1}] = (U, A). */
+/* One path p: n steps from X = 0, v = v0; writes (U, A) of date k = 1..n to
+ * out[(k-1) stride * 2 + {0,1}].  work holds 5 N doubles. */
+static void one_path(const orc_model *m, const double *L, double dt, int32_t n, int64_t p,
+                     uint64_t seed, double *work, double *out, int64_t stride)
+{
+    const int N = m->N;
+    double *X = work, *v = work + N, *eps = work + 2 * N, *eta = work + 3 * N, *ZS = work + 4 * N;
+    for (int a = 0; a < N; ++a) {
+        X[a] = 0.0;
+        v[a] = m->v0[a];
+    }
+    for (int32_t k = 0; k < n; ++k) {
+        orc_normals(N, seed, p, k, eps, eta);
+        for (int a = 0; a < N; ++a) {
+            double z = 0.0;
+            for (int b = 0; b <= a; ++b) z += L[a * N + b] * eps[b];
+            ZS[a] = z;
+        }
+        for (int a = 0; a < N; ++a) {
+            double rho = m->rho[a];
+            double Zv = rho * ZS[a] + sqrt(1.0 - rho * rho) * eta[a];
+            double vp = v[a] > 0.0 ? v[a] : 0.0;
+            double sq = sqrt(vp * dt);
+            X[a] = X[a] + (m->r - 0.5 * vp) * dt + sq * ZS[a];
+            v[a] = v[a] + m->kappa[a] * (m->theta[a] - vp) * dt + m->xi[a] * sq * Zv;
+        }
+        double U = -INFINITY, sv = 0.0;
+        for (int a = 0; a < N; ++a) {
+            double S = m->S0[a] * exp(X[a]);
+            if (S > U) U = S;
+            sv += v[a] > 0.0 ? v[a] : 0.0;
+        }
+        double *f = out + (int64_t)k * stride * 2;
+        f[0] = U;
+        f[1] = sv / (double)N;
+    }
+}
+
 int orc_features(const orc_model *m, const double *C, double T, int32_t n, int64_t P,
                  uint64_t seed, int32_t nthreads, double *feat)
 {
@@ -200,47 +238,43 @@ int orc_features(const orc_model *m, const double *C, double T, int32_t n, int64
 #endif
 #pragma omp parallel
     {
-        double *X = (double *)malloc(sizeof(double) * N * 5);
-        double *v = X + N, *eps = X + 2 * N, *eta = X + 3 * N, *ZS = X + 4 * N;
+        double *work = (double *)malloc(sizeof(double) * N * 5);
 #pragma omp for schedule(static)
         for (int64_t c = 0; c < nchunk; ++c) {
             int64_t pend = (c + 1) * ORC_CHUNK < P ? (c + 1) * ORC_CHUNK : P;
-            for (int64_t p = c * ORC_CHUNK; p < pend; ++p) {
-                for (int a = 0; a < N; ++a) {
-                    X[a] = 0.0;
-                    v[a] = m->v0[a];
-                }
-                for (int32_t k = 0; k < n; ++k) {
-                    orc_normals(N, seed, p, k, eps, eta);
-                    for (int a = 0; a < N; ++a) {
-                        double z = 0.0;
-                        for (int b = 0; b <= a; ++b) z += L[a * N + b] * eps[b];
-                        ZS[a] = z;
-                    }
-                    for (int a = 0; a < N; ++a) {
-                        double rho = m->rho[a];
-                        double Zv = rho * ZS[a] + sqrt(1.0 - rho * rho) * eta[a];
-                        double vp = v[a] > 0.0 ? v[a] : 0.0;
-                        double sq = sqrt(vp * dt);
-                        X[a] = X[a] + (m->r - 0.5 * vp) * dt + sq * ZS[a];
-                        v[a] = v[a] + m->kappa[a] * (m->theta[a] - vp) * dt + m->xi[a] * sq * Zv;
-                    }
-                    double U = -INFINITY, sv = 0.0;
-                    for (int a = 0; a < N; ++a) {
-                        double S = m->S0[a] * exp(X[a]);
-                        if (S > U) U = S;
-                        sv += v[a] > 0.0 ? v[a] : 0.0;
-                    }
-                    double *f = feat + ((int64_t)k * P + p) * 2;
-                    f[0] = U;
-                    f[1] = sv / (double)N;
-                }
-            }
+            for (int64_t p = c * ORC_CHUNK; p < pend; ++p)
+                one_path(m, L, dt, n, p, seed, work, feat + p * 2, P);
         }
-        free(X);
+        free(work);
     }
     free(L);
     return ORC_OK;
+}
+
+/* The same paths for a list of path indices (any p >= 0, so single paths of a
+ * large run can be checked): feat[(i n + k - 1) * 2 + {0,1}] for path paths[i]. */
+int orc_features_at(const orc_model *m, const double *C, double T, int32_t n, int64_t npaths,
+                    const int64_t *paths, uint64_t seed, double *feat)
+{
+    const int N = m->N;
+    if (N < 1 || n < 1 || npaths < 0 || !(T > 0.0)) return ORC_EINVAL;
+    double *L = (double *)malloc(sizeof(double) * N * N);
+    double *work = (double *)malloc(sizeof(double) * N * 5);
+    if (!L || !work) {
+        free(L); free(work);
+        return ORC_ENOMEM;
+    }
+    int st = orc_cholesky(N, C, L);
+    if (st == ORC_OK) {
+        const double dt = T / (double)n;
+        for (int64_t i = 0; i < npaths; ++i) {
+            if (paths[i] < 0) { st = ORC_EINVAL; break; }
+            one_path(m, L, dt, n, paths[i], seed, work, feat + i * (int64_t)n * 2, 1);
+        }
+    }
+    free(L);
+    free(work);
+    return st;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -188,3 +188,13 @@ def test_thread_count_invariance():
     b = oracle.lsmc(f1, w["option"], 0.02, tb, 5, nthreads=8)
     assert a["price"] == b["price"] and a["se"] == b["se"]
     assert np.array_equal(a["tau"], b["tau"])
+
+
+def test_features_at_equals_features():
+    # single paths of a run (used to check sampled paths of full-size GPU runs)
+    w = W.best_of_call(n_assets=4, n_paths=700, n_steps=9)
+    f = oracle.features(w["model"], w["corr"], 1.0, 9, 700, 42)
+    idx = [0, 1, 63, 64, 350, 699]
+    g = oracle.features_at(w["model"], w["corr"], 1.0, 9, idx, 42)
+    for i, p in enumerate(idx):
+        assert np.array_equal(g[i], f[:, p])
