@@ -101,7 +101,7 @@ void append_bytes(std::string& k, const T& v)
 
 // Everything one pass enqueues after its tables are uploaded.
 struct PassLaunch {
-    bool fp32 = true, american = true, cluster = false;
+    bool fp32 = true, american = true, cluster = false, keep = false;
     int nmax = 0, nchunks = 0, nbg = 0, Sp = 0, cluster_q = 0, per_launch = 0, sweep_q = 0;
     int64_t part_count = 0;
     PathArgs pa{};
@@ -127,7 +127,7 @@ hipError_t enqueue_pass(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
         ClusterArgs ca = L.ca;
         for (int s0 = 0; s0 < L.Sp; s0 += L.per_launch) {
             ca.s0 = s0;
-            if ((e = launch_sweep_cluster(L.fp32, L.cluster_q, L.la, ca,
+            if ((e = launch_sweep_cluster(L.fp32, L.cluster_q, L.keep, L.la, ca,
                                           std::min(L.per_launch, L.Sp - s0), st)) != hipSuccess)
                 return e;
         }
@@ -149,6 +149,7 @@ hipError_t launch_pass_graph(const PassLaunch& L, void* ws, hipStream_t st)
     append_bytes(key, L.fp32);
     append_bytes(key, L.american);
     append_bytes(key, L.cluster);
+    append_bytes(key, L.keep);
     append_bytes(key, L.nmax);
     append_bytes(key, L.nchunks);
     append_bytes(key, L.nbg);
@@ -304,6 +305,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         la.feat = pa.feat;
         la.reg = reinterpret_cast<RegRec*>(ws + pp.lay.reg);
         la.disc = reinterpret_cast<const double*>(ws + pp.lay.disc);
+        la.idisc = la.disc + static_cast<size_t>(Sp) * (q.n + 1);
         la.out = reinterpret_cast<double*>(ws + pp.lay.out);
         la.cf = reinterpret_cast<double*>(ws + pp.lay.cf);
         la.tau = reinterpret_cast<int32_t*>(ws + pp.lay.tau);
@@ -324,7 +326,11 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         L.cluster = sh.sweep == kSweepCluster;
         int cap = 0;
         if (L.cluster) {
-            cap = cluster_capacity(sh.fp32, sh.cluster_q, cluster_lds_bytes(q.n, sh.cluster_g));
+            // a Greek set that one workgroup per CU holds keeps the basis values
+            // in registers; a larger one fits two workgroups per CU without
+            L.keep = static_cast<int64_t>(Sp) * sh.cluster_g <= kPlanComputeUnits;
+            cap = cluster_capacity(sh.fp32, sh.cluster_q, L.keep,
+                                   cluster_lds_bytes(q.n, sh.cluster_g));
             if (cap < sh.cluster_g) {
                 if (q.opts.sweep_mode == 3) {
                     set_error("cluster sweep needs %d co-resident workgroups, the device holds %d",

@@ -889,18 +889,25 @@ __device__ __forceinline__ bool cluster_exchange(double (&b)[K], int m, double* 
     return true;
 }
 
-template <typename R, int Q>
-__global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArgs A,
+// KEEP: each path keeps the payoff and centred basis variables of the date it
+// last entered the regression, so that date's exercise decision needs no
+// recomputation (more registers: one workgroup per CU).  Otherwise the
+// decision recomputes them from that date's features, within 128 registers so
+// that two workgroups share a CU (4 waves per SIMD), for Greek sets larger
+// than one workgroup per CU can hold.  Both give the same numbers.
+template <typename R, int Q, bool KEEP>
+__global__ void __launch_bounds__(kClusterThreads,
+                                  (!KEEP && Q <= cluster_qmax_shared(sizeof(R) == 4)) ? 4 : 2)
+    k_sweep_cluster(const LsmcArgs A,
                                                                    const ClusterArgs C)
 {
     extern __shared__ unsigned char hs_smem[];
     constexpr int NW = kClusterThreads / 64;
     const int n = A.n;
     const int G = C.G;
-    double* const sdisc = reinterpret_cast<double*>(hs_smem);  // [n+1]
     ClusterLds Ls;
-    Ls.part = sdisc + ((n + 2) & ~1);                          // [2][NW][8]
-    Ls.tot = Ls.part + 2 * NW * kPartStride;                   // [2][8]
+    Ls.part = reinterpret_cast<double*>(hs_smem);   // [2][NW][8]
+    Ls.tot = Ls.part + 2 * NW * kPartStride;        // [2][8]
     Ls.flag = reinterpret_cast<int*>(Ls.tot + 2 * kPartStride);
     const int sl = blockIdx.x / G;
     const int g = blockIdx.x - sl * G;
@@ -908,8 +915,6 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     const int64_t P = A.P;
     const int m = A.m;
     const R2<R>* __restrict__ F = static_cast<const R2<R>*>(A.feat) + s * A.plane;
-    for (int j = threadIdx.x; j <= n; j += kClusterThreads)
-        sdisc[j] = A.disc[static_cast<int64_t>(s) * (n + 1) + j];
     if (threadIdx.x == 0) *Ls.flag = 1;
     __syncthreads();
 
@@ -919,41 +924,59 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
                          (static_cast<int64_t>(s) * cluster_rows(amer, n) - cluster_row0(amer, n)) *
                              row_len;
     const cptr<RegRec> recs = as_const<RegRec>(A.reg) + static_cast<int64_t>(s) * n;
+    const cptr<double> dsc = as_const<double>(A.disc) + static_cast<int64_t>(s) * (n + 1);
+    const cptr<double> idsc = as_const<double>(A.idisc) + static_cast<int64_t>(s) * (n + 1);
     const int64_t pbase = static_cast<int64_t>(g) * (kClusterThreads * Q) + threadIdx.x;
     const int64_t last = A.american ? static_cast<int64_t>(n - 1) * P : 0;
     int par = 0;
 
-    // path pbase + i kClusterThreads exists iff i < nlive (the last workgroup
-    // of a scenario may be ragged)
+    // State per path: the cash flow discounted to time 0, D = h_tau exp(-r tau
+    // dt).  The regression target at date k is D exp(r k dt) =
+    // h_tau exp(-r (tau - k) dt), and the price is the mean of D.  The exercise
+    // date tau, wanted only for export, goes straight to memory at each
+    // exercise (the sweep runs backward, so the last write is the earliest
+    // exercise date).
+    // Path pbase + i kClusterThreads exists iff i < nlive (the last workgroup
+    // of a scenario may be ragged).
     const int64_t room = P - pbase;
     const int nlive = room <= 0 ? 0 : (room + kClusterThreads - 1) / kClusterThreads;
-    double cf[Q];
-    int tau[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int64_t p = pbase + i * kClusterThreads;
-        cf[i] = i < nlive ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) : 0.0;
-        tau[i] = n;
-    }
-
-    double beta[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    double bcU = 0.0, bcA = 0.0;
-    bool have = false;  // beta of the later date k+1 is valid
-    double skipped = 0.0;
-    if (A.american) {
-        // pu/pa: features of date k+1 (its exercise decision); cu/ca: date k
-        // (this iteration's regression); nu/na: date k-1, loaded one iteration
-        // ago; the loads of date k-2 are issued during this iteration's exchange.
-        R cu[Q], ca[Q], pu[Q], pa[Q], nu[Q], na[Q];
+    int32_t* const tau = A.export_tau ? A.tau + static_cast<int64_t>(s) * P + pbase : nullptr;
+    double D[Q];
+    {
+        const double dn = dsc[n];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int64_t p = pbase + i * kClusterThreads;
-            pu[i] = R(0);
-            pa[i] = R(0);
+            D[i] = i < nlive ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) * dn : 0.0;
+            if (tau && i < nlive) tau[i * kClusterThreads] = n;
+        }
+    }
+
+    double beta[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    bool have = false;  // beta of the later date k+1 is valid
+    double skipped = 0.0;
+    if (A.american) {
+        // cu/ca: features of date k (this iteration's regression); nu/na: date
+        // k-1, loaded one iteration ago; fu/fa: date k-2, loaded after this
+        // iteration's exchange (without KEEP: date k+1 until its decision is
+        // taken, then date k-2).
+        R cu[Q], ca[Q], nu[Q], na[Q], fu[Q], fa[Q];
+        // payoff and centred basis variables of each path at the date last
+        // regressed, kept for that date's exercise decision (h = 0: out of
+        // the money, no decision)
+        double hh[Q], xx[Q], ww[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t p = pbase + i * kClusterThreads;
             cu[i] = R(0);
             ca[i] = R(0);
             nu[i] = R(0);
             na[i] = R(0);
+            fu[i] = R(0);
+            fa[i] = R(0);
+            hh[i] = 0.0;
+            xx[i] = 0.0;
+            ww[i] = 0.0;
             if (i < nlive && n >= 2) {
                 const R2<R> f = F[static_cast<int64_t>(n - 2) * P + p];
                 cu[i] = f.u;
@@ -969,6 +992,7 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
         double r_ok = n >= 2 ? recs[n - 2].ok : 0.0;
         double r_cU = n >= 2 ? recs[n - 2].cU : 0.0;
         double r_cA = n >= 2 ? recs[n - 2].cA : 0.0;
+        double bcU = 0.0, bcA = 0.0;  // regression-set means of date k+1
         for (int k = n - 1; k >= 1; --k) {
             const bool ok = r_ok != 0.0;
             const double cU = r_cU, cA = r_cA;
@@ -977,35 +1001,52 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
                 r_cU = recs[k - 2].cU;
                 r_cA = recs[k - 2].cA;
             }
-            // per path: exercise at date k+1 with its regression, then this
-            // date's right-hand side with the updated cash flow
+            const double d1 = dsc[k + 1], ik = idsc[k];
+            // per path: exercise at date k+1 with its regression (from the
+            // values kept at its regression), then this date's right-hand
+            // side with the updated cash flow
             double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 if (have) {
-                    const double U = static_cast<double>(pu[i]);
-                    const double h = payoff(A.cp, A.K, U);
-                    if (i < nlive && h > 0.0) {
+                    double h, x, w;
+                    if constexpr (KEEP) {
+                        h = hh[i];
+                        x = xx[i];
+                        w = ww[i];
+                    } else {
+                        const double U = static_cast<double>(fu[i]);
+                        h = i < nlive ? payoff(A.cp, A.K, U) : 0.0;
                         double phi[5];
-                        basis(m, U, static_cast<double>(pa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
-                        double cont = 0.0;
-#pragma unroll
-                        for (int q = 0; q < 5; ++q) cont += phi[q] * beta[q];
+                        basis(m, U, static_cast<double>(fa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
+                        x = phi[1];
+                        w = phi[3];
+                    }
+                    if (h > 0.0) {
+                        const double cont = beta[0] + beta[1] * x + beta[2] * (x * x) +
+                                            beta[3] * w + beta[4] * (x * w);
                         if (h > cont) {
-                            cf[i] = h;
-                            tau[i] = k + 1;
+                            D[i] = h * d1;
+                            if (tau) tau[i * kClusterThreads] = k + 1;
                         }
                     }
                 }
+                if constexpr (KEEP) hh[i] = 0.0;
                 if (ok) {
                     const double U = static_cast<double>(cu[i]);
-                    if (i < nlive && payoff(A.cp, A.K, U) > 0.0) {
+                    const double h = payoff(A.cp, A.K, U);
+                    if (i < nlive && h > 0.0) {
                         double phi[5];
                         basis(m, U, static_cast<double>(ca[i]), cU, cA, A.inv_K, A.inv_tbar, phi);
-                        const double Y = cf[i] * sdisc[tau[i] - k];
+                        const double Y = D[i] * ik;
 #pragma unroll
                         for (int q = 0; q < 5; ++q)
                             if (q < m) b[q] += phi[q] * Y;
+                        if constexpr (KEEP) {
+                            hh[i] = h;
+                            xx[i] = phi[1];
+                            ww[i] = phi[3];
+                        }
                     }
                 }
             }
@@ -1026,27 +1067,27 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
                 skipped += 1.0;
                 have = false;
             }
-            // date k+1 is decided: its registers take date k-2, used two
-            // iterations on.  Issued after the exchange, whose slot polls would
-            // otherwise wait for these loads (vector loads complete in order).
+            // date k-2 for two iterations on, issued after the exchange, whose
+            // slot polls would otherwise wait for these loads (vector loads
+            // complete in order)
             if (k > 2) {
                 const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 3) * P;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     if (i < nlive) {
                         const R2<R> f = Fn[pbase + i * kClusterThreads];
-                        pu[i] = f.u;
-                        pa[i] = f.a;
+                        fu[i] = f.u;
+                        fa[i] = f.a;
                     }
                 }
             }
-            // rotate: k becomes the decision date, k-1 the regression date, and
-            // the k-2 loads the next prefetched date
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const R tu = pu[i], ta = pa[i];
-                pu[i] = cu[i];
-                pa[i] = ca[i];
+                const R tu = fu[i], ta = fa[i];
+                if constexpr (!KEEP) {  // date k becomes the decision date
+                    fu[i] = cu[i];
+                    fa[i] = ca[i];
+                }
                 cu[i] = nu[i];
                 ca[i] = na[i];
                 nu[i] = tu;
@@ -1054,19 +1095,28 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
             }
         }
         if (have) {  // exercise at date 1
+            const double d1 = dsc[1];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const double U = static_cast<double>(pu[i]);
-                const double h = payoff(A.cp, A.K, U);
-                if (i < nlive && h > 0.0) {
+                double h, x, w;
+                if constexpr (KEEP) {
+                    h = hh[i];
+                    x = xx[i];
+                    w = ww[i];
+                } else {
+                    const double U = static_cast<double>(fu[i]);
+                    h = i < nlive ? payoff(A.cp, A.K, U) : 0.0;
                     double phi[5];
-                    basis(m, U, static_cast<double>(pa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
-                    double cont = 0.0;
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) cont += phi[q] * beta[q];
+                    basis(m, U, static_cast<double>(fa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
+                    x = phi[1];
+                    w = phi[3];
+                }
+                if (h > 0.0) {
+                    const double cont = beta[0] + beta[1] * x + beta[2] * (x * x) + beta[3] * w +
+                                        beta[4] * (x * w);
                     if (h > cont) {
-                        cf[i] = h;
-                        tau[i] = 1;
+                        D[i] = h * d1;
+                        if (tau) tau[i * kClusterThreads] = 1;
                     }
                 }
             }
@@ -1077,7 +1127,7 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     double s1[1] = {0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        if (i < nlive) s1[0] += cf[i] * sdisc[tau[i]];
+        if (i < nlive) s1[0] += D[i];
     if (!cluster_exchange<1>(s1, 1, part + static_cast<int64_t>(n) * row_len, G, g, par, C, Ls))
         return;
     par ^= 1;
@@ -1085,11 +1135,9 @@ __global__ void __launch_bounds__(kClusterThreads) k_sweep_cluster(const LsmcArg
     double s2[1] = {0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int64_t p = pbase + i * kClusterThreads;
         if (i < nlive) {
-            const double d = cf[i] * sdisc[tau[i]] - mean;
+            const double d = D[i] - mean;
             s2[0] += d * d;
-            if (A.export_tau) A.tau[static_cast<int64_t>(s) * P + p] = tau[i];
         }
     }
     if (!cluster_exchange<1>(s2, 1, part + static_cast<int64_t>(n + 1) * row_len, G, g, par, C,
@@ -1214,33 +1262,31 @@ hipError_t launch_sweep_r(int q, const LsmcArgs& a, int S, hipStream_t st)
     }
 }
 
-template <typename R, int Q>
+template <typename R, int Q, bool KEEP>
 hipError_t launch_cluster_t(const LsmcArgs& a, const ClusterArgs& c, int S_launch, size_t lds,
                             hipStream_t st)
 {
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&k_sweep_cluster<R, Q>),
+            reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, KEEP>),
             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_sweep_cluster<R, Q>), dim3(S_launch * c.G), dim3(kClusterThreads), lds,
-                       st, a, c);
+    hipLaunchKernelGGL((k_sweep_cluster<R, Q, KEEP>), dim3(S_launch * c.G),
+                       dim3(kClusterThreads), lds, st, a, c);
     return hipGetLastError();
 }
 
-template <typename R, int Q>
+template <typename R, int Q, bool KEEP>
 int cluster_capacity_t(size_t lds)
 {
-    if (lds > 65536 &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_cluster<R, Q>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(lds)) != hipSuccess)
+    const void* f = reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, KEEP>);
+    if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(lds)) != hipSuccess)
         return 0;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
-                                                     reinterpret_cast<const void*>(&k_sweep_cluster<R, Q>),
-                                                     kClusterThreads, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kClusterThreads, lds) !=
+        hipSuccess)
         return 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -1252,31 +1298,40 @@ int cluster_capacity_t(size_t lds)
 
 size_t cluster_lds_bytes(int n, int G)
 {
+    (void)n;
     (void)G;
-    return sizeof(double) * (((n + 2) & ~1) + 2 * (kClusterThreads / 64) * kPartStride +
-                             2 * kPartStride) + 16;
+    return sizeof(double) * (2 * (kClusterThreads / 64) * kPartStride + 2 * kPartStride) + 16;
 }
 
-int cluster_capacity(bool fp32, int q, size_t lds)
+int cluster_capacity(bool fp32, int q, bool keep, size_t lds)
 {
     switch (q) {
-    case 1: return fp32 ? cluster_capacity_t<float, 1>(lds) : cluster_capacity_t<double, 1>(lds);
-    case 2: return fp32 ? cluster_capacity_t<float, 2>(lds) : cluster_capacity_t<double, 2>(lds);
-    case 4: return fp32 ? cluster_capacity_t<float, 4>(lds) : cluster_capacity_t<double, 4>(lds);
-    case 8: return fp32 ? cluster_capacity_t<float, 8>(lds) : cluster_capacity_t<double, 8>(lds);
+#define HS_CAP(Q)                                                                        \
+    case Q:                                                                              \
+        return fp32 ? (keep ? cluster_capacity_t<float, Q, true>(lds)                    \
+                            : cluster_capacity_t<float, Q, false>(lds))                  \
+                    : (keep ? cluster_capacity_t<double, Q, true>(lds)                   \
+                            : cluster_capacity_t<double, Q, false>(lds));
+        HS_CAP(1) HS_CAP(2) HS_CAP(3) HS_CAP(4) HS_CAP(5) HS_CAP(6) HS_CAP(7) HS_CAP(8)
+#undef HS_CAP
     default: return 0;
     }
 }
 
-hipError_t launch_sweep_cluster(bool fp32, int q, const LsmcArgs& a, const ClusterArgs& c,
-                                int S_launch, hipStream_t st)
+hipError_t launch_sweep_cluster(bool fp32, int q, bool keep, const LsmcArgs& a,
+                                const ClusterArgs& c, int S_launch, hipStream_t st)
 {
     const size_t lds = cluster_lds_bytes(a.n, c.G);
     switch (q) {
-    case 1: return fp32 ? launch_cluster_t<float, 1>(a, c, S_launch, lds, st) : launch_cluster_t<double, 1>(a, c, S_launch, lds, st);
-    case 2: return fp32 ? launch_cluster_t<float, 2>(a, c, S_launch, lds, st) : launch_cluster_t<double, 2>(a, c, S_launch, lds, st);
-    case 4: return fp32 ? launch_cluster_t<float, 4>(a, c, S_launch, lds, st) : launch_cluster_t<double, 4>(a, c, S_launch, lds, st);
-    case 8: return fp32 ? launch_cluster_t<float, 8>(a, c, S_launch, lds, st) : launch_cluster_t<double, 8>(a, c, S_launch, lds, st);
+#define HS_LAUNCH(Q)                                                                    \
+    case Q:                                                                             \
+        return fp32 ? (keep ? launch_cluster_t<float, Q, true>(a, c, S_launch, lds, st)  \
+                            : launch_cluster_t<float, Q, false>(a, c, S_launch, lds, st)) \
+                    : (keep ? launch_cluster_t<double, Q, true>(a, c, S_launch, lds, st) \
+                            : launch_cluster_t<double, Q, false>(a, c, S_launch, lds, st));
+        HS_LAUNCH(1) HS_LAUNCH(2) HS_LAUNCH(3) HS_LAUNCH(4) HS_LAUNCH(5) HS_LAUNCH(6) HS_LAUNCH(7)
+        HS_LAUNCH(8)
+#undef HS_LAUNCH
     default: return hipErrorInvalidValue;
     }
 }

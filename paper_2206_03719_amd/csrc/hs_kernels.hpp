@@ -25,13 +25,14 @@ hipError_t launch_gram(bool fp32, const LsmcArgs& a, int S, hipStream_t st);
 int sweep_q_for(int64_t P);
 hipError_t launch_sweep(bool fp32, int q, const LsmcArgs& a, int S, hipStream_t st);
 
-// Cluster sweep: Q in {1,2,4,8} paths per thread, G workgroups per scenario,
-// S_launch scenarios (planes c.s0 ..) per launch; capacity = workgroups that
-// fit on the device at once.
+// Cluster sweep: Q in 1..8 paths per thread, G workgroups per scenario,
+// S_launch scenarios (planes c.s0 ..) per launch; keep = each path keeps its
+// basis values between a date's regression and its decision (more registers);
+// capacity = workgroups that fit on the device at once.
 size_t cluster_lds_bytes(int n, int G);
-int cluster_capacity(bool fp32, int q, size_t lds);
-hipError_t launch_sweep_cluster(bool fp32, int q, const LsmcArgs& a, const ClusterArgs& c,
-                                int S_launch, hipStream_t st);
+int cluster_capacity(bool fp32, int q, bool keep, size_t lds);
+hipError_t launch_sweep_cluster(bool fp32, int q, bool keep, const LsmcArgs& a,
+                                const ClusterArgs& c, int S_launch, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st);
 
 hipError_t launch_philox_words(uint64_t seed, int64_t P, int n, int nb, uint32_t* out,

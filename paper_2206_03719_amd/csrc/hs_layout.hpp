@@ -77,6 +77,7 @@ struct LsmcArgs {
     const void* feat;      // R2 planes [scen][date][path]
     RegRec* reg;           // [scen][date] (date index k-1 for date k)
     const double* disc;    // [scen][n+1] exp(-r j dt), host libm
+    const double* idisc;   // [scen][n+1] exp(+r j dt), host libm
     double* out;           // [scen][4]: price, se, skipped, itm-count
     double* cf;            // [scen][P] (state in workspace), else null
     int32_t* tau;          // [scen][P] state / export, or null
@@ -92,6 +93,10 @@ struct LsmcArgs {
 constexpr int kClusterThreads = 512;
 constexpr int kPartStride = 8;  // doubles per published workgroup partial
 constexpr int kMaxClusterGroups = 1024;
+constexpr int kPlanComputeUnits = 256;  // MI355X: the cluster sweep plans for this many CUs
+// Most paths per thread with which a workgroup of the cluster sweep that does
+// not keep basis values fits 128 registers (two workgroups per CU).
+constexpr int cluster_qmax_shared(bool fp32) { return fp32 ? 7 : 4; }
 
 // Partial slots start as kEmptySlot (a NaN bit pattern that arithmetic never
 // produces); a workgroup's published partial is the slot's only write.

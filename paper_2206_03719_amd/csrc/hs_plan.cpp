@@ -356,18 +356,24 @@ Shape shape_of(const Request& q)
     sh.american = q.opt.style == HS_AMERICAN;
     sh.nmax = paths_nmax_bucket(q.N);
     sh.tmax = paths_tmax(sh.fp32, sh.nmax);
-    // cluster sweep shape from the path count alone (never from device load)
+    // cluster sweep shape from the request alone (never from device load, nor
+    // from the workspace): spread the Greek set's scenarios over the compute
+    // units, from one path per thread up to 8
     const int64_t P = q.P;
-    int cq = 8;
-    if (P <= kClusterThreads)
-        cq = 1;
-    else if (P <= 2 * kClusterThreads)
-        cq = 2;
-    else if (P <= 4 * kClusterThreads)
-        cq = 4;
+    const int64_t T = kClusterThreads;
+    const int64_t S = num_scenarios(q.N, q.bumps.mask);
+    int64_t gmin = (P + 8 * T - 1) / (8 * T);
+    // more workgroups than one per CU: throughput-bound, two workgroups per CU,
+    // which bounds the paths per thread
+    if (S * gmin > kPlanComputeUnits) {
+        const int64_t qs = cluster_qmax_shared(q.opts.precision == HS_FP32_PATHS);
+        gmin = (P + qs * T - 1) / (qs * T);
+    }
+    const int64_t gone = (P + T - 1) / T;
+    int64_t G = std::max(gmin, std::min(std::max<int64_t>(1, kPlanComputeUnits / std::max<int64_t>(S, 1)), gone));
+    const int cq = static_cast<int>((P + G * T - 1) / (G * T));
+    G = (P + cq * T - 1) / (cq * T);
     sh.cluster_q = cq;
-    const int64_t G = (P + static_cast<int64_t>(cq) * kClusterThreads - 1) /
-                      (static_cast<int64_t>(cq) * kClusterThreads);
     sh.cluster_g = static_cast<int>(G);
     const int mode = q.opts.sweep_mode;
     if (mode == 1) {
@@ -398,8 +404,8 @@ Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, in
                              (sh.fp32 ? sizeof(TaskP<float>) : sizeof(TaskP<double>)));
     L.groups = off;
     off = align_up(off + static_cast<size_t>(std::max(n_groups, 1)) * sizeof(GroupP));
-    L.disc = off;
-    off = align_up(off + S * (q.n + 1) * sizeof(double));
+    L.disc = off;  // exp(-r j dt), then exp(+r j dt)
+    off = align_up(off + 2 * S * (q.n + 1) * sizeof(double));
     L.reg = off;
     off = align_up(off + (sh.american ? S * q.n * sizeof(RegRec) : 0));
     L.out = off;
@@ -556,13 +562,18 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
         fill_tables<float>(q, sh, sc, pass, gs, pp);
     else
         fill_tables<double>(q, sh, sc, pass, gs, pp);
-    // discount factors exp(-r j dt), j = 0..n, per scenario of the pass
+    // discount factors exp(-r j dt), j = 0..n, per scenario of the pass, then
+    // their inverses exp(+r j dt)
     const int n = q.n;
-    pp.disc.resize(pass.scen.size() * (n + 1));
-    for (size_t i = 0; i < pass.scen.size(); ++i) {
+    const size_t ns = pass.scen.size();
+    pp.disc.resize(2 * ns * (n + 1));
+    for (size_t i = 0; i < ns; ++i) {
         const Scenario& s = sc[pass.scen[i]];
         const double dt = s.T / static_cast<double>(n);
-        for (int j = 0; j <= n; ++j) pp.disc[i * (n + 1) + j] = std::exp(-s.r * static_cast<double>(j) * dt);
+        for (int j = 0; j <= n; ++j) {
+            pp.disc[i * (n + 1) + j] = std::exp(-s.r * static_cast<double>(j) * dt);
+            pp.disc[(ns + i) * (n + 1) + j] = std::exp(s.r * static_cast<double>(j) * dt);
+        }
     }
     pp.lay = layout_for(q, sh, static_cast<int>(pass.scen.size()), pp.ntasks,
                         static_cast<int>(pp.groups.size()));

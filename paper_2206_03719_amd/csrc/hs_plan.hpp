@@ -79,7 +79,7 @@ struct PassPlan {
     std::vector<unsigned char> base;    // BaseP<R>
     std::vector<unsigned char> tasks;   // TaskP<R>[]
     std::vector<GroupP> groups;         // [nbg * W]
-    std::vector<double> disc;           // [scen][n+1]
+    std::vector<double> disc;           // [scen][n+1] exp(-r j dt), then [scen][n+1] exp(+r j dt)
     int W = 1, nbg = 1, nchunks = 1, ntasks = 0;
     Layout lay;
 };
