@@ -54,6 +54,8 @@ def lib(path=None):
         L.orc_features.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int32,
                                    ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, dp]
         L.orc_features.restype = ctypes.c_int
+        L.orc_qe_variance_step.argtypes = [ctypes.c_double] * 7
+        L.orc_qe_variance_step.restype = ctypes.c_double
         L.orc_features_at.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int32,
                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_uint64, dp]
@@ -114,11 +116,14 @@ def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+SCHEMES = {"euler": 0, "qe": 1}
+
+
 class _Model(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32),
                 ("S0", ctypes.c_void_p), ("v0", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("rho", ctypes.c_void_p),
-                ("r", ctypes.c_double)]
+                ("r", ctypes.c_double), ("scheme", ctypes.c_int32)]
 
 
 class _Request(ctypes.Structure):
@@ -132,7 +137,7 @@ class _Request(ctypes.Structure):
                 ("spot_rel", ctypes.c_double), ("v0_rel", ctypes.c_double),
                 ("T_abs", ctypes.c_double), ("r_abs", ctypes.c_double),
                 ("corr_abs", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("nthreads", ctypes.c_int32)]
+                ("nthreads", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
 
 # ---------------------------------------------------------------------------
@@ -174,17 +179,17 @@ def cholesky(C):
     return L
 
 
-def _model_struct(model, keep):
+def _model_struct(model, keep, scheme="euler"):
     arrs = [_f64(model[k]) for k in ("S0", "v0", "kappa", "theta", "xi", "rho")]
     keep.extend(arrs)
-    m = _Model(len(arrs[0]), *[a.ctypes.data for a in arrs], float(model["r"]))
+    m = _Model(len(arrs[0]), *[a.ctypes.data for a in arrs], float(model["r"]), SCHEMES[scheme])
     return m
 
 
-def features(model, corr, T, n_steps, n_paths, seed, nthreads=0):
+def features(model, corr, T, n_steps, n_paths, seed, nthreads=0, scheme="euler"):
     """(n_steps, n_paths, 2) array of (U, A) at dates 1..n for one scenario."""
     keep = []
-    m = _model_struct(model, keep)
+    m = _model_struct(model, keep, scheme)
     C = _f64(corr)
     out = np.empty((n_steps, n_paths, 2))
     st = lib().orc_features(ctypes.byref(m), _dp(C), float(T), int(n_steps), int(n_paths),
@@ -194,11 +199,11 @@ def features(model, corr, T, n_steps, n_paths, seed, nthreads=0):
     return out
 
 
-def features_at(model, corr, T, n_steps, paths, seed):
+def features_at(model, corr, T, n_steps, paths, seed, scheme="euler"):
     """(len(paths), n_steps, 2) array of (U, A) at dates 1..n for the given path
     indices of one scenario (the same paths as features() produces)."""
     keep = []
-    m = _model_struct(model, keep)
+    m = _model_struct(model, keep, scheme)
     C = _f64(corr)
     idx = np.ascontiguousarray(np.asarray(paths, dtype=np.int64))
     out = np.empty((len(idx), n_steps, 2))
@@ -252,8 +257,14 @@ def num_scenarios(n_assets, mask):
     return int(lib().orc_num_scenarios(int(n_assets), int(mask)))
 
 
+def qe_variance_step(kappa, theta, xi, rho, dt, v, zv):
+    """One quadratic-exponential variance step from v with normal zv."""
+    return lib().orc_qe_variance_step(float(kappa), float(theta), float(xi), float(rho),
+                                      float(dt), float(v), float(zv))
+
+
 def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed, nthreads=0,
-                 export_tau=False, replay_tau=None):
+                 export_tau=False, replay_tau=None, scheme="euler"):
     """The full Greek set: scenario prices, SEs, skipped counts and the Greeks.
 
     replay_tau (scenarios x paths int32): price each scenario with these
@@ -269,7 +280,8 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed, nthreads=0,
                  _CP[option["cp"]], _STYLE[option["style"]], m, float(option["K"]),
                  float(option["T"]), int(n_paths), int(n_steps), mask,
                  float(bumps["spot_rel"]), float(bumps["v0_rel"]), float(bumps["T_abs"]),
-                 float(bumps["r_abs"]), float(bumps["corr_abs"]), int(seed), int(nthreads))
+                 float(bumps["r_abs"]), float(bumps["corr_abs"]), int(seed), int(nthreads),
+                 SCHEMES[scheme])
     S = num_scenarios(N, mask)
     prices = np.zeros(S)
     ses = np.zeros(S)

@@ -159,12 +159,91 @@ int orc_cholesky(int32_t N, const double *C, double *L)
 }
 
 /* ------------------------------------------------------------------------ */
-/* One scenario of the model. */
+/* One scenario of the model.  scheme: ORC_EULER_FT or ORC_QE. */
+#define ORC_EULER_FT 0
+#define ORC_QE 1
 typedef struct {
     int32_t N;
     const double *S0, *v0, *kappa, *theta, *xi, *rho;
     double r;
+    int32_t scheme;
 } orc_model;
+
+/* ------------------------------------------------------------------------ */
+/* Andersen's quadratic-exponential (QE) step (Andersen 2008, the scheme the
+ * paper's STAC-A2 code uses, Sec. 2.2 and 2.2.1), written from its definition.
+ *
+ * Variance: the next variance is drawn from a distribution with the exact
+ * conditional mean m and variance s^2 of the CIR process over dt,
+ *   m = theta + (v - theta) e^{-kappa dt},
+ *   s^2 = v xi^2 e^{-kappa dt} (1 - e^{-kappa dt}) / kappa
+ *         + theta xi^2 (1 - e^{-kappa dt})^2 / (2 kappa),
+ * chosen by psi = s^2 / m^2 against psi_c = 1.5:
+ *   psi <= psi_c: v' = a (b + Z_v)^2 with b^2 = 2/psi - 1 + sqrt(2/psi)
+ *                 sqrt(2/psi - 1) and a = m / (1 + b^2);
+ *   psi > psi_c:  p = (psi - 1)/(psi + 1), beta = (1 - p)/m, and with the
+ *                 uniform U = Phi(Z_v): v' = 0 if U <= p, else
+ *                 ln((1 - p)/(1 - U)) / beta.
+ * (xi = 0: s^2 = 0 and v' = m.)  Log price, with gamma1 = gamma2 = 1/2:
+ *   X' = X + r dt + K0 + K1 v + K2 v' + sqrt(K3 v + K4 v') Z_x,
+ *   K0 = -rho kappa theta dt / xi, K1 = gamma1 dt (kappa rho/xi - 1/2) - rho/xi,
+ *   K2 = gamma2 dt (kappa rho/xi - 1/2) + rho/xi, K3 = gamma1 dt (1 - rho^2),
+ *   K4 = gamma2 dt (1 - rho^2)  (rho/xi read as 0 when xi = 0, which the
+ *   interface allows only with rho = 0).
+ * Random inputs per asset and step (the paper's two numbers per element):
+ * Z_x = (L eps)_i, correlated across assets, and Z_v = eta_i, independent;
+ * the spot-variance correlation enters through the K coefficients. */
+#define ORC_PSI_C 1.5
+
+typedef struct {
+    double E, mth, c1, c2, K0, K1, K2, K3, K4;
+} qe_consts;
+
+static void qe_consts_for(double kappa, double theta, double xi, double rho, double r, double dt,
+                          qe_consts *q)
+{
+    const double E = exp(-kappa * dt);
+    const double f = kappa > 0.0 ? -expm1(-kappa * dt) / kappa : dt; /* (1 - E)/kappa */
+    const double g1 = 0.5, g2 = 0.5;
+    const double rx = xi > 0.0 ? rho / xi : 0.0;
+    q->E = E;
+    q->mth = theta * (1.0 - E);
+    q->c1 = xi * xi * E * f;
+    q->c2 = 0.5 * theta * xi * xi * (1.0 - E) * f;
+    q->K0 = r * dt - rx * kappa * theta * dt;
+    q->K1 = g1 * dt * (kappa * rx - 0.5) - rx;
+    q->K2 = g2 * dt * (kappa * rx - 0.5) + rx;
+    q->K3 = g1 * dt * (1.0 - rho * rho);
+    q->K4 = g2 * dt * (1.0 - rho * rho);
+}
+
+static double qe_variance(const qe_consts *q, double v, double zv)
+{
+    const double m = q->mth + v * q->E;
+    const double s2 = v * q->c1 + q->c2;
+    if (!(s2 > 0.0)) return m;
+    const double psi = s2 / (m * m);
+    if (psi <= ORC_PSI_C) {
+        const double t = 2.0 / psi;
+        const double b2 = t - 1.0 + sqrt(t) * sqrt(t - 1.0);
+        const double a = m / (1.0 + b2);
+        const double b = sqrt(b2);
+        return a * (b + zv) * (b + zv);
+    }
+    const double p = (psi - 1.0) / (psi + 1.0);
+    const double beta = (1.0 - p) / m;
+    const double u = 0.5 * erfc(-zv / sqrt(2.0));
+    return u <= p ? 0.0 : log((1.0 - p) / (1.0 - u)) / beta;
+}
+
+/* One QE step of the variance from v with normal zv (test access). */
+double orc_qe_variance_step(double kappa, double theta, double xi, double rho, double dt, double v,
+                            double zv)
+{
+    qe_consts q;
+    qe_consts_for(kappa, theta, xi, rho, 0.0, dt, &q);
+    return qe_variance(&q, v, zv);
+}
 
 /* Heston paths and the per-date LS path reduction for one scenario.
  *
@@ -173,9 +252,12 @@ typedef struct {
  *   + xi_i sqrt(v_i) dW^v_i.
  * Correlation: Z^S = L eps with L = chol(C); Z^v_i = rho_i Z^S_i +
  * sqrt(1 - rho_i^2) eta_i.
- * Scheme: full-truncation Euler (Lord, Koekkoek & van Dijk 2010) in log price:
+ * Scheme ORC_EULER_FT: full-truncation Euler (Lord, Koekkoek & van Dijk 2010)
+ * in log price:
  *   v+ = max(v, 0);  X += (r - v+/2) dt + sqrt(v+ dt) Z^S;
  *   v += kappa (theta - v+) dt + xi sqrt(v+ dt) Z^v;  S = S0 exp(X), X_0 = 0.
+ * Scheme ORC_QE: the quadratic-exponential step above, with Z_x = Z^S and
+ * Z_v = eta (v stays >= 0, so max(v, 0) = v).
  * Reduction at each date k = 1..n (Sec. 4.1): U = max_i S_i (U = S for one
  * asset) and A = (1/N) sum_i max(v_i, 0).
  * Output feat[((k-1) P + p) * 2 + {0,1}] = (U, A). */
@@ -197,6 +279,15 @@ static void one_path(const orc_model *m, const double *L, double dt, int32_t n, 
             for (int b = 0; b <= a; ++b) z += L[a * N + b] * eps[b];
             ZS[a] = z;
         }
+        if (m->scheme == ORC_QE) {
+            for (int a = 0; a < N; ++a) {
+                qe_consts q;
+                qe_consts_for(m->kappa[a], m->theta[a], m->xi[a], m->rho[a], m->r, dt, &q);
+                const double vn = qe_variance(&q, v[a], eta[a]);
+                X[a] = X[a] + q.K0 + q.K1 * v[a] + q.K2 * vn + sqrt(q.K3 * v[a] + q.K4 * vn) * ZS[a];
+                v[a] = vn;
+            }
+        } else
         for (int a = 0; a < N; ++a) {
             double rho = m->rho[a];
             double Zv = rho * ZS[a] + sqrt(1.0 - rho * rho) * eta[a];
@@ -540,6 +631,7 @@ typedef struct {
     double spot_rel, v0_rel, T_abs, r_abs, corr_abs;
     uint64_t seed;
     int32_t nthreads;
+    int32_t scheme;
 } orc_request;
 
 /* Prices of every scenario of the Greek set.  prices/ses/skipped have
@@ -611,7 +703,7 @@ int orc_price_scenarios_replay(const orc_request *q, double *prices, double *ses
             }
             if (!done) { st = ORC_EINVAL; break; }
         }
-        orc_model mm = {N, S0, v0, q->kappa, q->theta, q->xi, q->rho, r};
+        orc_model mm = {N, S0, v0, q->kappa, q->theta, q->xi, q->rho, r, q->scheme};
         st = orc_features(&mm, C, T, q->n, q->P, q->seed, q->nthreads, feat);
         if (st != ORC_OK) break;
         double out[2];

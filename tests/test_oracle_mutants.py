@@ -12,6 +12,7 @@ from oracle import build as obuild
 
 import test_oracle_lsmc as TL
 import test_oracle_model as TM
+import test_oracle_qe as TQ
 import test_oracle_rng as TR
 
 # (name, exact source text, its replacement, pins expected to catch it)
@@ -94,6 +95,31 @@ MUTANTS = [
      "C[i * N + j] += q->corr_abs;", [TL.test_correlation_greek_vs_stulz]),
     ("rate-bump-ignored", "if (idx == 0) { r = q->r + q->r_abs; done = 1; }",
      "if (idx == 0) { r = q->r; done = 1; }", [TL.test_greeks_black_scholes_limit]),
+    # Andersen QE step
+    ("qe-b2-sign", "const double b2 = t - 1.0 + sqrt(t) * sqrt(t - 1.0);",
+     "const double b2 = t - 1.0 - sqrt(t) * sqrt(t - 1.0);",
+     [lambda: TQ.test_variance_step_matches_cir_moments(0.09)]),
+    ("qe-a-without-b2", "const double a = m / (1.0 + b2);", "const double a = m / b2;",
+     [lambda: TQ.test_variance_step_matches_cir_moments(0.09)]),
+    ("qe-p-inverted", "const double p = (psi - 1.0) / (psi + 1.0);",
+     "const double p = (psi + 1.0) / (psi - 1.0) - 1.0;",
+     [lambda: TQ.test_variance_step_matches_cir_moments(0.0005)]),
+    ("qe-beta-upside-down", "const double beta = (1.0 - p) / m;", "const double beta = m / (1.0 - p);",
+     [lambda: TQ.test_variance_step_matches_cir_moments(0.0005)]),
+    ("qe-s2-second-term-dropped", "q->c2 = 0.5 * theta * xi * xi * (1.0 - E) * f;", "q->c2 = 0.0;",
+     [lambda: TQ.test_variance_step_matches_cir_moments(0.0)]),
+    ("qe-mean-reverts-to-zero", "q->mth = theta * (1.0 - E);", "q->mth = 0.0;",
+     [TQ.test_zero_vol_of_vol_is_deterministic]),
+    ("qe-trapezoid-one-sided", "q->K3 = g1 * dt * (1.0 - rho * rho);", "q->K3 = 2.0 * g1 * dt * (1.0 - rho * rho);",
+     [TQ.test_time_dependent_variance]),
+    ("qe-rho-sign", "const double rx = xi > 0.0 ? rho / xi : 0.0;", "const double rx = xi > 0.0 ? -rho / xi : 0.0;",
+     [lambda: TQ.test_heston_semi_closed_form(0.04, 2.0, 0.04, 0.3, -0.7, (80.0, 100.0, 120.0))]),
+    ("qe-kappa-term-in-K2-dropped", "q->K2 = g2 * dt * (kappa * rx - 0.5) + rx;",
+     "q->K2 = g2 * dt * (-0.5) + rx;",
+     [lambda: TQ.test_heston_semi_closed_form(0.04, 1.0, 0.04, 1.0, -0.5, (70.0, 100.0, 130.0))]),
+    ("qe-uniform-from-wrong-tail", "const double u = 0.5 * erfc(-zv / sqrt(2.0));",
+     "const double u = 0.5 * erfc(zv / sqrt(2.0));",
+     [lambda: TQ.test_variance_step_matches_cir_moments(0.0005), TQ.test_variance_step_branches]),
 ]
 
 
