@@ -90,6 +90,22 @@ typedef int32_t hs_status;
 #define HS_FP64 0
 #define HS_FP32_PATHS 1
 
+/* opts.scheme: the time step of the Heston paths (Sec. 2.2 and 2.2.1).
+ *   EULER_FT: full-truncation Euler in log price, v+ = max(v, 0):
+ *     X += (r - v+/2) dt + sqrt(v+ dt) Z^S;
+ *     v += kappa (theta - v+) dt + xi sqrt(v+ dt) (rho Z^S + sqrt(1-rho^2) eta).
+ *   QE: Andersen's quadratic-exponential step, the benchmark's own scheme:
+ *     the next variance matches the CIR conditional mean m and variance s^2
+ *     (psi = s^2/m^2 <= 1.5: a (b + eta)^2; else 0 with probability
+ *     p = (psi-1)/(psi+1), otherwise exponential with mean m/(1-p), drawn
+ *     with the uniform Phi(eta)); log price
+ *     X += r dt + K0 + K1 v + K2 v' + sqrt(K3 v + K4 v') Z^S with
+ *     gamma1 = gamma2 = 1/2.  Needs xi_i > 0 or rho_i = 0 for every asset.
+ * Z^S = L eps in both, with (eps, eta) the Box-Muller pairs of the same
+ * Philox counters, so both schemes consume identical random numbers. */
+#define HS_SCHEME_EULER_FT 0
+#define HS_SCHEME_QE 1
+
 /* opts.flags */
 #define HS_FLAG_EXPORT_TAU 1u /* write each path's exercise date into greeks.tau */
 #define HS_FLAG_TIMING 2u     /* fill greeks.t_*_ms with per-stage device times  */
@@ -137,7 +153,8 @@ typedef struct hs_opts {
                                 registers (n_paths <= 16384), 2 = one workgroup per scenario
                                 with the state in the workspace, 3 = cluster of workgroups per
                                 scenario (HS_EDEVICE if it cannot be co-resident)          */
-    int32_t reserved[4];     /* must be zero                                       */
+    int32_t scheme;          /* HS_SCHEME_EULER_FT (0) | HS_SCHEME_QE (1)          */
+    int32_t reserved[3];     /* must be zero                                       */
 } hs_opts;
 
 /* Results of a Greek set.  Caller-allocated host arrays; any may be NULL to

@@ -22,6 +22,8 @@ BASIS_AUTO, BASIS_QUAD, BASIS_QUAD_VOL = 0, 1, 2
 BUMP_DELTA_GAMMA, BUMP_VEGA, BUMP_THETA, BUMP_RHO, BUMP_CORR, BUMP_ALL = 1, 2, 4, 8, 16, 31
 FP64, FP32_PATHS = 0, 1
 FLAG_EXPORT_TAU, FLAG_TIMING, FLAG_GRAPH = 1, 2, 4
+SCHEME_EULER_FT, SCHEME_QE = 0, 1
+SCHEMES = {"euler": SCHEME_EULER_FT, "qe": SCHEME_QE}
 MAX_ASSETS = 20
 
 _CP = {"put": PUT, "call": CALL}
@@ -62,7 +64,8 @@ class Bumps(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("sweep_mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("sweep_mode", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Greeks(ctypes.Structure):
@@ -162,7 +165,7 @@ class _Marshal:
     """Holds the numpy arrays the ctypes structs point into."""
 
     def __init__(self, model, corr, option, bumps=None, seed=42, precision="fp32", flags=0,
-                 waves_per_block=0, sweep_mode=0):
+                 waves_per_block=0, sweep_mode=0, scheme="euler"):
         self.arrs = [_f64(model[k]) for k in ("S0", "v0", "kappa", "theta", "xi", "rho")]
         N = len(self.arrs[0])
         self.N = N
@@ -179,7 +182,8 @@ class _Marshal:
                            float(b["T_abs"]), float(b["r_abs"]), float(b["corr_abs"]))
         prec = _PREC[precision] if isinstance(precision, str) else int(precision)
         self.opts = Opts(prec, int(waves_per_block), int(seed), int(flags), int(sweep_mode),
-                         (ctypes.c_int32 * 4)(0, 0, 0, 0))
+                         SCHEMES[scheme] if isinstance(scheme, str) else int(scheme),
+                         (ctypes.c_int32 * 3)(0, 0, 0))
 
     @property
     def corr_ptr(self):
@@ -192,9 +196,9 @@ def num_scenarios(n_assets, mask):
 
 
 def workspace_bytes(model, option, n_paths, n_steps, bumps, precision="fp32", minimum=False,
-                    flags=0, sweep_mode=0):
+                    flags=0, sweep_mode=0, scheme="euler"):
     m = _Marshal(model, np.eye(len(model["S0"])), option, bumps, precision=precision,
-                 flags=flags, sweep_mode=sweep_mode)
+                 flags=flags, sweep_mode=sweep_mode, scheme=scheme)
     f = lib().hs_workspace_min_bytes if minimum else lib().hs_workspace_bytes
     n = f(ctypes.byref(m.model), ctypes.byref(m.option), int(n_paths), int(n_steps),
           ctypes.byref(m.bumps), ctypes.byref(m.opts))
@@ -216,7 +220,7 @@ def _stream_handle(stream):
 
 def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="fp32",
                  workspace=None, stream=None, export_tau=False, timing=False,
-                 waves_per_block=0, sweep_mode=0, graph=False):
+                 waves_per_block=0, sweep_mode=0, graph=False, scheme="euler"):
     """Price + bump-and-revalue Greeks of one option (hs_price_greeks).
 
     ``workspace``: a CUDA uint8 tensor (allocated here when None).  ``graph``:
@@ -225,11 +229,12 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precisio
     torch = _torch()
     flags = ((FLAG_EXPORT_TAU if export_tau else 0) | (FLAG_TIMING if timing else 0) |
              (FLAG_GRAPH if graph else 0))
-    m = _Marshal(model, corr, option, bumps, seed, precision, flags, waves_per_block, sweep_mode)
+    m = _Marshal(model, corr, option, bumps, seed, precision, flags, waves_per_block, sweep_mode,
+                 scheme)
     N = m.N
     if workspace is None:
         nbytes = workspace_bytes(model, option, n_paths, n_steps, bumps, precision, flags=flags,
-                                 sweep_mode=sweep_mode)
+                                 sweep_mode=sweep_mode, scheme=scheme)
         workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     S = num_scenarios(N, m.bumps.mask)
     out_arrays = {"delta": np.zeros(N), "gamma": np.zeros(N), "vega": np.zeros(N),
@@ -259,11 +264,11 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precisio
 
 
 def autotune(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="fp32",
-             workspace=None, stream=None, repeats=3):
+             workspace=None, stream=None, repeats=3, scheme="euler"):
     """Times the path kernel's launch shapes on this request class and stores
     the fastest for later calls (hs_autotune).  Returns the best ms per set."""
     torch = _torch()
-    m = _Marshal(model, corr, option, bumps, seed, precision)
+    m = _Marshal(model, corr, option, bumps, seed, precision, scheme=scheme)
     if workspace is None:
         nbytes = workspace_bytes(model, option, n_paths, n_steps, bumps, precision)
         workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -276,12 +281,13 @@ def autotune(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="f
     return best.value
 
 
-def path_features(model, corr, T, n_paths, n_steps, seed=42, precision="fp64", stream=None):
+def path_features(model, corr, T, n_paths, n_steps, seed=42, precision="fp64", stream=None,
+                  scheme="euler"):
     """Heston paths + per-date path reduction of the base model
     (hs_path_features): a CUDA tensor [n_steps, n_paths, 2] of (U, A)."""
     torch = _torch()
     m = _Marshal(model, corr, {"cp": "call", "style": "american", "K": 1.0, "T": T},
-                 None, seed, precision)
+                 None, seed, precision, scheme=scheme)
     dtype = torch.float64 if m.opts.precision == FP64 else torch.float32
     out = torch.empty((n_steps, n_paths, 2), dtype=dtype, device="cuda")
     wsb = int(lib().hs_path_features_workspace_bytes(m.N))
@@ -330,7 +336,7 @@ class Server:
 
     def submit(self, w, precision=None):
         m = _Marshal(w["model"], w["corr"], w["option"], w["bumps"], w.get("seed", 42),
-                     precision or w.get("precision", "fp32"))
+                     precision or w.get("precision", "fp32"), scheme=w.get("scheme", "euler"))
         req = Request(m.model, m.corr_ptr, m.option, int(w["n_paths"]), int(w["n_steps"]),
                       m.bumps, m.opts)
         t = ctypes.c_uint64()

@@ -66,10 +66,11 @@ int default_target_waves() { return 3072; }
 namespace {
 
 struct TuneKey {
-    int N, log2P, n_bucket, S, fp32;
+    int N, log2P, n_bucket, S, fp32, scheme;
     bool operator<(const TuneKey& o) const
     {
-        return std::tie(N, log2P, n_bucket, S, fp32) < std::tie(o.N, o.log2P, o.n_bucket, o.S, o.fp32);
+        return std::tie(N, log2P, n_bucket, S, fp32, scheme) <
+               std::tie(o.N, o.log2P, o.n_bucket, o.S, o.fp32, o.scheme);
     }
 };
 
@@ -83,7 +84,7 @@ TuneKey tune_key(const Request& q)
     int nb = 0;
     while ((1 << (nb + 1)) <= q.n) ++nb;
     return {q.N, lp, nb, static_cast<int>(num_scenarios(q.N, q.bumps.mask)),
-            q.opts.precision == HS_FP32_PATHS ? 1 : 0};
+            q.opts.precision == HS_FP32_PATHS ? 1 : 0, q.opts.scheme};
 }
 
 // ---------------------------------------------------------------------------
@@ -102,6 +103,7 @@ void append_bytes(std::string& k, const T& v)
 // Everything one pass enqueues after its tables are uploaded.
 struct PassLaunch {
     bool fp32 = true, american = true, cluster = false, keep = false;
+    int scheme = HS_SCHEME_EULER_FT;
     int nmax = 0, nchunks = 0, nbg = 0, Sp = 0, cluster_q = 0, per_launch = 0, sweep_q = 0;
     int64_t part_count = 0;
     PathArgs pa{};
@@ -116,7 +118,8 @@ hipError_t enqueue_pass(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.err_flag), 1, 0, st)) != hipSuccess)
         return e;
-    if ((e = launch_paths(L.fp32, L.nmax, L.pa, L.nchunks, L.nbg, st)) != hipSuccess) return e;
+    if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.pa, L.nchunks, L.nbg, st)) != hipSuccess)
+        return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
     if (L.american && (e = launch_gram(L.fp32, L.la, L.Sp, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
@@ -151,6 +154,7 @@ hipError_t launch_pass_graph(const PassLaunch& L, void* ws, hipStream_t st)
     append_bytes(key, L.cluster);
     append_bytes(key, L.keep);
     append_bytes(key, L.nmax);
+    append_bytes(key, L.scheme);
     append_bytes(key, L.nchunks);
     append_bytes(key, L.nbg);
     append_bytes(key, L.Sp);
@@ -284,6 +288,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         L.fp32 = sh.fp32;
         L.american = sh.american;
         L.nmax = sh.nmax;
+        L.scheme = q.opts.scheme;
         L.nchunks = pp.nchunks;
         L.nbg = pp.nbg;
         L.Sp = Sp;
@@ -600,7 +605,8 @@ hs_status hs_path_features(const hs_model* model, const double* corr, int64_t n_
     pa.store_all = 1;
     pa.key0 = static_cast<uint32_t>(q.opts.seed);
     pa.key1 = static_cast<uint32_t>(q.opts.seed >> 32);
-    HS_HIP(launch_paths(sh.fp32, sh.nmax, pa, pp.nchunks, pp.nbg, st), "path kernel launch");
+    HS_HIP(launch_paths(sh.fp32, sh.nmax, q.opts.scheme, pa, pp.nchunks, pp.nbg, st),
+           "path kernel launch");
     // the host tables must outlive the asynchronous uploads
     HS_HIP(hipStreamSynchronize(st), "stream synchronize");
     return HS_OK;

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "../../include/hs_api.h"
 #include "hs_kernels.hpp"
 #include "hs_layout.hpp"
 
@@ -105,6 +106,15 @@ __device__ __forceinline__ double exp_r(double x) { return exp(x); }
 __device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 
+// FP32: hardware log2 and reciprocal; FP64: the library / IEEE division.
+__device__ __forceinline__ float log_r(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
+__device__ __forceinline__ double log_r(double x) { return log(x); }
+__device__ __forceinline__ float div_r(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double div_r(double a, double b) { return a / b; }
+// standard normal distribution function
+__device__ __forceinline__ float ncdf_r(float z) { return 0.5f * erfcf(-z * 0.707106781186548f); }
+__device__ __forceinline__ double ncdf_r(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
 template <typename R>
 struct alignas(2 * sizeof(R)) R2 {
     R u, a;
@@ -140,6 +150,41 @@ __device__ __forceinline__ R pick(const R (&arr)[NM], int i)
 }
 
 // ---------------------------------------------------------------------------
+// Andersen's quadratic-exponential step of one asset from (X, v) with the
+// correlated normal zx and the independent normal zv (constants c: QeP).  The
+// CIR conditional mean m and variance s^2 and the branch test psi <= 1.5 are
+// FP64 in both path precisions (the branch is a discrete choice; both sides
+// of a comparison with the oracle take it in FP64); the rest runs in R.
+template <typename R, typename CP>
+__device__ __forceinline__ void qe_step(CP c, R zx, R zv, R& X, R& v)
+{
+    const double vd = static_cast<double>(v);
+    const double m = c->mth + vd * c->E;
+    const double s2 = vd * c->c1 + c->c2;
+    R vn;
+    if (!(s2 > 0.0)) {
+        vn = static_cast<R>(m);
+    } else {
+        const double psi = s2 / (m * m);
+        const R ps = static_cast<R>(psi), mr = static_cast<R>(m);
+        if (psi <= 1.5) {
+            const R t = div_r(R(2), ps);
+            const R b2 = t - R(1) + sqrt_r(t) * sqrt_r(t - R(1));
+            const R a = div_r(mr, R(1) + b2);
+            const R b = sqrt_r(b2);
+            vn = a * (b + zv) * (b + zv);
+        } else {
+            const R pm = div_r(ps - R(1), ps + R(1));
+            const R beta = div_r(R(1) - pm, mr);
+            const R u = ncdf_r(zv);
+            vn = u <= pm ? R(0) : div_r(log_r(div_r(R(1) - pm, R(1) - u)), beta);
+        }
+    }
+    X = X + c->K0 + c->K1 * v + c->K2 * vn + sqrt_r(c->K3 * v + c->K4 * vn) * zx;
+    v = vn;
+}
+
+// ---------------------------------------------------------------------------
 // Path kernel.
 //
 // Block = W waves x 64 lanes; lane l of every wave follows path
@@ -147,7 +192,7 @@ __device__ __forceinline__ R pick(const R (&arr)[NM], int i)
 // wave) of tasks.  LDS holds, double-buffered by step parity, the step's
 // normals (eps, eta), the base scenario's correlated normals Z^S, exp(X) and
 // max(v, 0), each [asset][lane].
-template <typename R, int NMAX, int TMAX>
+template <typename R, int NMAX, int TMAX, int SCHEME>
 __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 {
     extern __shared__ unsigned char hs_smem[];
@@ -225,11 +270,15 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                 R z = R(0);
                 for (int b = 0; b <= a; ++b) z += bp->L[a * kMaxAssets + b] * s_eps[b * kLanes + lane];
                 const cptr<AssetP<R>> q = bp->a + a;
-                const R zv = q->rho * z + q->rhobar * s_eta[a * kLanes + lane];
-                const R vp = Vo[i] > R(0) ? Vo[i] : R(0);
-                const R sq = sqrt_r(vp * dt);
-                Xo[i] = Xo[i] + (r - half * vp) * dt + sq * z;
-                Vo[i] = Vo[i] + q->kappa * (q->theta - vp) * dt + q->xi * sq * zv;
+                if constexpr (SCHEME == HS_SCHEME_QE) {
+                    qe_step(&q->qe, z, s_eta[a * kLanes + lane], Xo[i], Vo[i]);
+                } else {
+                    const R zv = q->rho * z + q->rhobar * s_eta[a * kLanes + lane];
+                    const R vp = Vo[i] > R(0) ? Vo[i] : R(0);
+                    const R sq = sqrt_r(vp * dt);
+                    Xo[i] = Xo[i] + (r - half * vp) * dt + sq * z;
+                    Vo[i] = Vo[i] + q->kappa * (q->theta - vp) * dt + q->xi * sq * zv;
+                }
                 s_zs[a * kLanes + lane] = z;
                 s_e[a * kLanes + lane] = exp_r(Xo[i]);
                 s_vp[a * kLanes + lane] = Vo[i] > R(0) ? Vo[i] : R(0);
@@ -313,11 +362,15 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                 } else {
                     z = s_zs[a * kLanes + lane];
                 }
-                const R zv = T->rho * z + T->rhobar * s_eta[a * kLanes + lane];
-                const R vp = tV[t] > R(0) ? tV[t] : R(0);
-                const R sq = sqrt_r(vp * T->dt);
-                tX[t] = tX[t] + (T->r - half * vp) * T->dt + sq * z;
-                tV[t] = tV[t] + T->kappa * (T->theta - vp) * T->dt + T->xi * sq * zv;
+                if constexpr (SCHEME == HS_SCHEME_QE) {
+                    qe_step(&T->qe, z, s_eta[a * kLanes + lane], tX[t], tV[t]);
+                } else {
+                    const R zv = T->rho * z + T->rhobar * s_eta[a * kLanes + lane];
+                    const R vp = tV[t] > R(0) ? tV[t] : R(0);
+                    const R sq = sqrt_r(vp * T->dt);
+                    tX[t] = tX[t] + (T->r - half * vp) * T->dt + sq * z;
+                    tV[t] = tV[t] + T->kappa * (T->theta - vp) * T->dt + T->xi * sq * zv;
+                }
                 const R S = T->S0 * exp_r(tX[t]);
                 const R vpt = tV[t] > R(0) ? tV[t] : R(0);
                 if (T->first) {
@@ -1205,37 +1258,37 @@ __global__ void k_normals(uint32_t k0, uint32_t k1, int N, int64_t P, int n, R* 
     }
 }
 
-template <typename R, int NMAX, int TMAX>
+template <typename R, int NMAX, int TMAX, int SCHEME>
 hipError_t launch_paths_t(const PathArgs& a, int nchunks, int nbg, hipStream_t st)
 {
     const size_t lds = 2u * 5u * NMAX * kLanes * sizeof(R);
     if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_paths<R, NMAX, TMAX>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_paths<R, NMAX, TMAX, SCHEME>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
     dim3 grid(nchunks, nbg), block(kLanes, a.W);
-    hipLaunchKernelGGL((k_paths<R, NMAX, TMAX>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((k_paths<R, NMAX, TMAX, SCHEME>), grid, block, lds, st, a);
     return hipGetLastError();
 }
 
-template <typename R>
+template <typename R, int SCHEME>
 hipError_t launch_paths_r(int nmax, const PathArgs& a, int nchunks, int nbg, hipStream_t st)
 {
     constexpr bool F = sizeof(R) == 4;
     switch (nmax) {
-    case 1: return launch_paths_t<R, 1, F ? 32 : 16>(a, nchunks, nbg, st);
-    case 2: return launch_paths_t<R, 2, F ? 32 : 16>(a, nchunks, nbg, st);
-    case 3: return launch_paths_t<R, 3, F ? 32 : 16>(a, nchunks, nbg, st);
-    case 4: return launch_paths_t<R, 4, F ? 32 : 16>(a, nchunks, nbg, st);
-    case 5: return launch_paths_t<R, 5, F ? 32 : 16>(a, nchunks, nbg, st);
-    case 6: return launch_paths_t<R, 6, F ? 32 : 16>(a, nchunks, nbg, st);
-    case 8: return launch_paths_t<R, 8, F ? 32 : 16>(a, nchunks, nbg, st);
-    case 10: return launch_paths_t<R, 10, F ? 24 : 16>(a, nchunks, nbg, st);
-    case 12: return launch_paths_t<R, 12, F ? 24 : 16>(a, nchunks, nbg, st);
-    case 16: return launch_paths_t<R, 16, F ? 20 : 16>(a, nchunks, nbg, st);
-    case 20: return launch_paths_t<R, 20, 20>(a, nchunks, nbg, st);
+    case 1: return launch_paths_t<R, 1, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 2: return launch_paths_t<R, 2, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 3: return launch_paths_t<R, 3, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 4: return launch_paths_t<R, 4, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 5: return launch_paths_t<R, 5, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 6: return launch_paths_t<R, 6, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 8: return launch_paths_t<R, 8, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 10: return launch_paths_t<R, 10, F ? 24 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 12: return launch_paths_t<R, 12, F ? 24 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 16: return launch_paths_t<R, 16, F ? 20 : 16, SCHEME>(a, nchunks, nbg, st);
+    case 20: return launch_paths_t<R, 20, 20, SCHEME>(a, nchunks, nbg, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1364,11 +1417,14 @@ size_t paths_lds_bytes(bool fp32, int nmax)
     return 2u * 5u * static_cast<size_t>(nmax) * kLanes * (fp32 ? 4u : 8u);
 }
 
-hipError_t launch_paths(bool fp32, int nmax, const PathArgs& a, int nchunks, int nbg,
+hipError_t launch_paths(bool fp32, int nmax, int scheme, const PathArgs& a, int nchunks, int nbg,
                         hipStream_t st)
 {
-    return fp32 ? launch_paths_r<float>(nmax, a, nchunks, nbg, st)
-                : launch_paths_r<double>(nmax, a, nchunks, nbg, st);
+    if (scheme == HS_SCHEME_QE)
+        return fp32 ? launch_paths_r<float, HS_SCHEME_QE>(nmax, a, nchunks, nbg, st)
+                    : launch_paths_r<double, HS_SCHEME_QE>(nmax, a, nchunks, nbg, st);
+    return fp32 ? launch_paths_r<float, HS_SCHEME_EULER_FT>(nmax, a, nchunks, nbg, st)
+                : launch_paths_r<double, HS_SCHEME_EULER_FT>(nmax, a, nchunks, nbg, st);
 }
 
 template <typename R>

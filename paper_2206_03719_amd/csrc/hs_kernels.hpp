@@ -14,8 +14,8 @@ namespace hs {
 int paths_nmax_bucket(int N);
 int paths_tmax(bool fp32, int nmax);
 size_t paths_lds_bytes(bool fp32, int nmax);
-hipError_t launch_paths(bool fp32, int nmax, const PathArgs& a, int nchunks, int nblockgroups,
-                        hipStream_t st);
+hipError_t launch_paths(bool fp32, int nmax, int scheme, const PathArgs& a, int nchunks,
+                        int nblockgroups, hipStream_t st);
 
 // Gram matrices and their Cholesky factors for dates 1..n-1 of S scenarios.
 hipError_t launch_gram(bool fp32, const LsmcArgs& a, int S, hipStream_t st);

@@ -16,10 +16,22 @@ constexpr int kGramThreads = 256; // Gram kernel block
 constexpr int kSweepThreads = 1024;
 constexpr int kRegRec = 20;       // doubles per (scenario, date) regression record
 
+// Quadratic-exponential step constants of one asset of one scenario (host
+// FP64): E = exp(-kappa dt), mth = theta (1 - E), c1, c2 with the CIR
+// conditional variance s^2 = v c1 + c2, and the log-price coefficients
+// K0 (with r dt), K1..K4.  The branch test psi = s^2/m^2 <= 1.5 runs in FP64
+// in both path precisions.
+template <typename R>
+struct QeP {
+    double E, mth, c1, c2;
+    R K0, K1, K2, K3, K4, pad[3];
+};
+
 // One asset of the base scenario.  rhobar = sqrt(1 - rho^2) (host FP64).
 template <typename R>
 struct AssetP {
     R S0, v0, kappa, theta, xi, rho, rhobar, pad;
+    QeP<R> qe;
 };
 
 // The base scenario, in the path precision R.
@@ -41,6 +53,7 @@ struct TaskP {
     int32_t asset, own_row, first, last, scen, lo, hi, pad;
     R S0, v0, kappa, theta, xi, rho, rhobar, r, dt, pad1;
     R L[kMaxAssets];  // the scenario's Cholesky row of `asset` (own_row == 1)
+    QeP<R> qe;
 };
 
 // One wave's share of a block: its tasks, and whether it writes the base and

@@ -247,11 +247,22 @@ hs_status validate(const Request& q)
         set_error("opts.sweep_mode = 1 needs n_paths <= %d", 16 * kSweepThreads);
         return HS_EINVAL;
     }
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (op.reserved[i] != 0) {
             set_error("opts.reserved must be zero");
             return HS_EINVAL;
         }
+    if (op.scheme != HS_SCHEME_EULER_FT && op.scheme != HS_SCHEME_QE) {
+        set_error("opts.scheme = %d", op.scheme);
+        return HS_EINVAL;
+    }
+    if (op.scheme == HS_SCHEME_QE)
+        for (int a = 0; a < q.N; ++a)
+            if (!(q.xi[a] > 0.0) && q.rho[a] != 0.0) {
+                set_error("QE needs xi > 0 or rho = 0 (asset %d: xi = %g, rho = %g)", a, q.xi[a],
+                          q.rho[a]);
+                return HS_EINVAL;
+            }
     return HS_OK;
 }
 
@@ -430,6 +441,31 @@ Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, in
 
 namespace {
 
+// Andersen's QE constants for one asset over one step dt (host FP64):
+// E = e^{-kappa dt}; m = mth + v E and s^2 = v c1 + c2 are the CIR conditional
+// mean and variance; K0 (with r dt) .. K4 the central (gamma = 1/2) log-price
+// coefficients, with rho/xi read as 0 when xi = 0 (validation then demands
+// rho = 0).
+template <typename R>
+QeP<R> qe_params(double kappa, double theta, double xi, double rho, double r, double dt)
+{
+    QeP<R> c;
+    std::memset(&c, 0, sizeof c);
+    const double E = std::exp(-kappa * dt);
+    const double f = kappa > 0.0 ? -std::expm1(-kappa * dt) / kappa : dt;  // (1 - E)/kappa
+    const double rx = xi > 0.0 ? rho / xi : 0.0;
+    c.E = E;
+    c.mth = theta * (1.0 - E);
+    c.c1 = xi * xi * E * f;
+    c.c2 = 0.5 * theta * xi * xi * (1.0 - E) * f;
+    c.K0 = static_cast<R>(r * dt - rx * kappa * theta * dt);
+    c.K1 = static_cast<R>(0.5 * dt * (kappa * rx - 0.5) - rx);
+    c.K2 = static_cast<R>(0.5 * dt * (kappa * rx - 0.5) + rx);
+    c.K3 = static_cast<R>(0.5 * dt * (1.0 - rho * rho));
+    c.K4 = static_cast<R>(0.5 * dt * (1.0 - rho * rho));
+    return c;
+}
+
 template <typename R>
 void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,
                  const Pass& pass, const std::vector<std::vector<int>>& group_scen, PassPlan& pp)
@@ -446,6 +482,8 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
         bp.a[a].xi = static_cast<R>(q.xi[a]);
         bp.a[a].rho = static_cast<R>(q.rho[a]);
         bp.a[a].rhobar = static_cast<R>(std::sqrt(1.0 - q.rho[a] * q.rho[a]));
+        bp.a[a].qe = qe_params<R>(q.kappa[a], q.theta[a], q.xi[a], q.rho[a], q.r,
+                                  q.opt.T / static_cast<double>(q.n));
         for (int c = 0; c < N; ++c) bp.L[a * kMaxAssets + c] = static_cast<R>(b0.L[a * N + c]);
         bp.S0_up[a] = static_cast<R>(q.S0[a] * (1.0 + q.bumps.spot_rel));
         bp.S0_dn[a] = static_cast<R>(q.S0[a] * (1.0 - q.bumps.spot_rel));
@@ -495,6 +533,8 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
                 t.rhobar = static_cast<R>(std::sqrt(1.0 - q.rho[a] * q.rho[a]));
                 t.r = static_cast<R>(s.r);
                 t.dt = static_cast<R>(s.T / static_cast<double>(q.n));
+                t.qe = qe_params<R>(q.kappa[a], q.theta[a], q.xi[a], q.rho[a], s.r,
+                                    s.T / static_cast<double>(q.n));
                 for (int c = 0; c < N; ++c) t.L[c] = static_cast<R>(s.L[a * N + c]);
                 tasks.push_back(t);
             }

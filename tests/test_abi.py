@@ -142,3 +142,17 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(hs, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         hs.lib()
+
+
+def test_scheme_validation():
+    w = W.best_of_call(n_paths=1000, n_steps=16)
+    assert _call(w, opts__scheme=2)[0] == hs.EINVAL
+    # QE needs xi > 0 or rho = 0
+    w2 = dict(w)
+    w2["model"] = {k: (np.array(v, copy=True) if k != "r" else v) for k, v in w["model"].items()}
+    w2["model"]["xi"][1] = 0.0
+    st, msg = _call(w2, opts__scheme=1)
+    assert st == hs.EINVAL and "QE" in msg
+    w2["model"]["rho"][1] = 0.0
+    assert _call(w2, opts__scheme=1, ws_bytes=4096)[0] == hs.ENOMEM  # valid, tiny workspace
+    assert _call(w, opts__reserved=(ctypes.c_int32 * 3)(0, 1, 0))[0] == hs.EINVAL
