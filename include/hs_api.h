@@ -106,6 +106,17 @@ typedef int32_t hs_status;
 #define HS_SCHEME_EULER_FT 0
 #define HS_SCHEME_QE 1
 
+/* opts.feature_format: how the per-date path features (U, A) are stored in
+ * the workspace between the path kernel and the regression.  NATIVE: in the
+ * path precision (8 B per path-step in FP32, 16 B in FP64).  FP16 / BF16:
+ * rounded to nearest-even half or bfloat16 (4 B per path-step), a study of
+ * reduced-precision storage in the spirit of the paper's numeric-
+ * representation experiments (Sec. 4.2, Table 4); FP32 paths with the
+ * EULER_FT scheme only.  The regression still reads them into FP64. */
+#define HS_FEATURES_NATIVE 0
+#define HS_FEATURES_FP16 1
+#define HS_FEATURES_BF16 2
+
 /* opts.flags */
 #define HS_FLAG_EXPORT_TAU 1u /* write each path's exercise date into greeks.tau */
 #define HS_FLAG_TIMING 2u     /* fill greeks.t_*_ms with per-stage device times  */
@@ -154,7 +165,9 @@ typedef struct hs_opts {
                                 with the state in the workspace, 3 = cluster of workgroups per
                                 scenario (HS_EDEVICE if it cannot be co-resident)          */
     int32_t scheme;          /* HS_SCHEME_EULER_FT (0) | HS_SCHEME_QE (1)          */
-    int32_t reserved[3];     /* must be zero                                       */
+    int32_t feature_format;  /* HS_FEATURES_NATIVE (0) | HS_FEATURES_FP16 (1) |
+                                HS_FEATURES_BF16 (2)                               */
+    int32_t reserved[2];     /* must be zero                                       */
 } hs_opts;
 
 /* Results of a Greek set.  Caller-allocated host arrays; any may be NULL to
@@ -220,7 +233,8 @@ hs_status hs_price_greeks(const hs_model *model, const double *corr, const hs_op
 /* The paper's measured kernel on its own (Sec. 2.2.1 and 4.1): Heston paths
  * of the base model and, at each date k = 1..n_steps, the path reduction
  * U = max_i S_i and A = (1/N) sum_i max(v_i, 0).  Output d_out (device):
- * [n_steps][n_paths][2] of double (HS_FP64) or float (HS_FP32_PATHS).
+ * [n_steps][n_paths][2] of double (HS_FP64), float (HS_FP32_PATHS), or
+ * half / bfloat16 with opts.feature_format FP16 / BF16.
  * d_workspace: device, >= hs_path_features_workspace_bytes.  Enqueued only;
  * the call does not synchronize. */
 size_t hs_path_features_workspace_bytes(int32_t n_assets);

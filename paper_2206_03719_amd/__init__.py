@@ -24,6 +24,8 @@ FP64, FP32_PATHS = 0, 1
 FLAG_EXPORT_TAU, FLAG_TIMING, FLAG_GRAPH = 1, 2, 4
 SCHEME_EULER_FT, SCHEME_QE = 0, 1
 SCHEMES = {"euler": SCHEME_EULER_FT, "qe": SCHEME_QE}
+FEATURES_NATIVE, FEATURES_FP16, FEATURES_BF16 = 0, 1, 2
+FEATURES = {"native": FEATURES_NATIVE, "fp16": FEATURES_FP16, "bf16": FEATURES_BF16}
 MAX_ASSETS = 20
 
 _CP = {"put": PUT, "call": CALL}
@@ -65,7 +67,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("sweep_mode", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("feature_format", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Greeks(ctypes.Structure):
@@ -165,7 +167,7 @@ class _Marshal:
     """Holds the numpy arrays the ctypes structs point into."""
 
     def __init__(self, model, corr, option, bumps=None, seed=42, precision="fp32", flags=0,
-                 waves_per_block=0, sweep_mode=0, scheme="euler"):
+                 waves_per_block=0, sweep_mode=0, scheme="euler", features="native"):
         self.arrs = [_f64(model[k]) for k in ("S0", "v0", "kappa", "theta", "xi", "rho")]
         N = len(self.arrs[0])
         self.N = N
@@ -183,7 +185,8 @@ class _Marshal:
         prec = _PREC[precision] if isinstance(precision, str) else int(precision)
         self.opts = Opts(prec, int(waves_per_block), int(seed), int(flags), int(sweep_mode),
                          SCHEMES[scheme] if isinstance(scheme, str) else int(scheme),
-                         (ctypes.c_int32 * 3)(0, 0, 0))
+                         FEATURES[features] if isinstance(features, str) else int(features),
+                         (ctypes.c_int32 * 2)(0, 0))
 
     @property
     def corr_ptr(self):
@@ -196,9 +199,9 @@ def num_scenarios(n_assets, mask):
 
 
 def workspace_bytes(model, option, n_paths, n_steps, bumps, precision="fp32", minimum=False,
-                    flags=0, sweep_mode=0, scheme="euler"):
+                    flags=0, sweep_mode=0, scheme="euler", features="native"):
     m = _Marshal(model, np.eye(len(model["S0"])), option, bumps, precision=precision,
-                 flags=flags, sweep_mode=sweep_mode, scheme=scheme)
+                 flags=flags, sweep_mode=sweep_mode, scheme=scheme, features=features)
     f = lib().hs_workspace_min_bytes if minimum else lib().hs_workspace_bytes
     n = f(ctypes.byref(m.model), ctypes.byref(m.option), int(n_paths), int(n_steps),
           ctypes.byref(m.bumps), ctypes.byref(m.opts))
@@ -220,7 +223,8 @@ def _stream_handle(stream):
 
 def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="fp32",
                  workspace=None, stream=None, export_tau=False, timing=False,
-                 waves_per_block=0, sweep_mode=0, graph=False, scheme="euler"):
+                 waves_per_block=0, sweep_mode=0, graph=False, scheme="euler",
+                 features="native"):
     """Price + bump-and-revalue Greeks of one option (hs_price_greeks).
 
     ``workspace``: a CUDA uint8 tensor (allocated here when None).  ``graph``:
@@ -230,11 +234,11 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precisio
     flags = ((FLAG_EXPORT_TAU if export_tau else 0) | (FLAG_TIMING if timing else 0) |
              (FLAG_GRAPH if graph else 0))
     m = _Marshal(model, corr, option, bumps, seed, precision, flags, waves_per_block, sweep_mode,
-                 scheme)
+                 scheme, features)
     N = m.N
     if workspace is None:
         nbytes = workspace_bytes(model, option, n_paths, n_steps, bumps, precision, flags=flags,
-                                 sweep_mode=sweep_mode, scheme=scheme)
+                                 sweep_mode=sweep_mode, scheme=scheme, features=features)
         workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     S = num_scenarios(N, m.bumps.mask)
     out_arrays = {"delta": np.zeros(N), "gamma": np.zeros(N), "vega": np.zeros(N),
@@ -282,13 +286,14 @@ def autotune(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="f
 
 
 def path_features(model, corr, T, n_paths, n_steps, seed=42, precision="fp64", stream=None,
-                  scheme="euler"):
+                  scheme="euler", features="native"):
     """Heston paths + per-date path reduction of the base model
     (hs_path_features): a CUDA tensor [n_steps, n_paths, 2] of (U, A)."""
     torch = _torch()
     m = _Marshal(model, corr, {"cp": "call", "style": "american", "K": 1.0, "T": T},
-                 None, seed, precision, scheme=scheme)
-    dtype = torch.float64 if m.opts.precision == FP64 else torch.float32
+                 None, seed, precision, scheme=scheme, features=features)
+    dtype = {FEATURES_FP16: torch.float16, FEATURES_BF16: torch.bfloat16}.get(
+        m.opts.feature_format, torch.float64 if m.opts.precision == FP64 else torch.float32)
     out = torch.empty((n_steps, n_paths, 2), dtype=dtype, device="cuda")
     wsb = int(lib().hs_path_features_workspace_bytes(m.N))
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
@@ -336,7 +341,8 @@ class Server:
 
     def submit(self, w, precision=None):
         m = _Marshal(w["model"], w["corr"], w["option"], w["bumps"], w.get("seed", 42),
-                     precision or w.get("precision", "fp32"), scheme=w.get("scheme", "euler"))
+                     precision or w.get("precision", "fp32"), scheme=w.get("scheme", "euler"),
+                     features=w.get("features", "native"))
         req = Request(m.model, m.corr_ptr, m.option, int(w["n_paths"]), int(w["n_steps"]),
                       m.bumps, m.opts)
         t = ctypes.c_uint64()

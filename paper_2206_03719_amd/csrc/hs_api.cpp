@@ -104,6 +104,7 @@ void append_bytes(std::string& k, const T& v)
 struct PassLaunch {
     bool fp32 = true, american = true, cluster = false, keep = false;
     int scheme = HS_SCHEME_EULER_FT;
+    int feat = kFeatF32;
     int nmax = 0, nchunks = 0, nbg = 0, Sp = 0, cluster_q = 0, per_launch = 0, sweep_q = 0;
     int64_t part_count = 0;
     PathArgs pa{};
@@ -118,10 +119,11 @@ hipError_t enqueue_pass(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.err_flag), 1, 0, st)) != hipSuccess)
         return e;
-    if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.pa, L.nchunks, L.nbg, st)) != hipSuccess)
+    if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.feat, L.pa, L.nchunks, L.nbg, st)) !=
+        hipSuccess)
         return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if (L.american && (e = launch_gram(L.fp32, L.la, L.Sp, st)) != hipSuccess) return e;
+    if (L.american && (e = launch_gram(L.feat, L.la, L.Sp, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     if (L.cluster) {
         if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.ca.partials), L.part_count,
@@ -130,12 +132,12 @@ hipError_t enqueue_pass(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
         ClusterArgs ca = L.ca;
         for (int s0 = 0; s0 < L.Sp; s0 += L.per_launch) {
             ca.s0 = s0;
-            if ((e = launch_sweep_cluster(L.fp32, L.cluster_q, L.keep, L.la, ca,
+            if ((e = launch_sweep_cluster(L.feat, L.cluster_q, L.keep, L.la, ca,
                                           std::min(L.per_launch, L.Sp - s0), st)) != hipSuccess)
                 return e;
         }
     } else {
-        if ((e = launch_sweep(L.fp32, L.sweep_q, L.la, L.Sp, st)) != hipSuccess) return e;
+        if ((e = launch_sweep(L.feat, L.sweep_q, L.la, L.Sp, st)) != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
     return hipSuccess;
@@ -155,6 +157,7 @@ hipError_t launch_pass_graph(const PassLaunch& L, void* ws, hipStream_t st)
     append_bytes(key, L.keep);
     append_bytes(key, L.nmax);
     append_bytes(key, L.scheme);
+    append_bytes(key, L.feat);
     append_bytes(key, L.nchunks);
     append_bytes(key, L.nbg);
     append_bytes(key, L.Sp);
@@ -289,6 +292,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         L.american = sh.american;
         L.nmax = sh.nmax;
         L.scheme = q.opts.scheme;
+        L.feat = sh.feat;
         L.nchunks = pp.nchunks;
         L.nbg = pp.nbg;
         L.Sp = Sp;
@@ -334,7 +338,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
             // a Greek set that one workgroup per CU holds keeps the basis values
             // in registers; a larger one fits two workgroups per CU without
             L.keep = static_cast<int64_t>(Sp) * sh.cluster_g <= kPlanComputeUnits;
-            cap = cluster_capacity(sh.fp32, sh.cluster_q, L.keep,
+            cap = cluster_capacity(sh.feat, sh.cluster_q, L.keep,
                                    cluster_lds_bytes(q.n, sh.cluster_g));
             if (cap < sh.cluster_g) {
                 if (q.opts.sweep_mode == 3) {
@@ -571,7 +575,7 @@ hs_status hs_path_features(const hs_model* model, const double* corr, int64_t n_
     rc = expand_scenarios(q, sc);
     if (rc != HS_OK) return rc;
     const Shape sh = shape_of(q);
-    const size_t need = static_cast<size_t>(n_steps) * n_paths * 2 * (sh.fp32 ? 4 : 8);
+    const size_t need = static_cast<size_t>(n_steps) * n_paths * feat_bytes(sh.feat);
     if (out_bytes < need) {
         set_error("hs_path_features: output needs %zu bytes, got %zu", need, out_bytes);
         return HS_ENOMEM;
@@ -605,7 +609,7 @@ hs_status hs_path_features(const hs_model* model, const double* corr, int64_t n_
     pa.store_all = 1;
     pa.key0 = static_cast<uint32_t>(q.opts.seed);
     pa.key1 = static_cast<uint32_t>(q.opts.seed >> 32);
-    HS_HIP(launch_paths(sh.fp32, sh.nmax, q.opts.scheme, pa, pp.nchunks, pp.nbg, st),
+    HS_HIP(launch_paths(sh.fp32, sh.nmax, q.opts.scheme, sh.feat, pa, pp.nchunks, pp.nbg, st),
            "path kernel launch");
     // the host tables must outlive the asynchronous uploads
     HS_HIP(hipStreamSynchronize(st), "stream synchronize");

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/hs_api.h"
 #include "hs_kernels.hpp"
@@ -101,6 +102,20 @@ __device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, double& e, 
 
 // FP32: e^x = 2^(x log2 e) on v_exp_f32, and v_sqrt_f32 (arguments here are
 // >= 0 and far from overflow); FP64: the library functions.
+// Box-Muller with eta in FP64 and eps in R (the QE variance path's normal).
+__device__ __forceinline__ void box_muller_mixed(uint32_t w1, uint32_t w2, float& e, double& h)
+{
+    const double R = sqrt(-2.0 * log(unit_f64(w1)));
+    double sn, cs;
+    sincospi(2.0 * unit_f64(w2), &sn, &cs);
+    e = static_cast<float>(R * cs);
+    h = R * sn;
+}
+__device__ __forceinline__ void box_muller_mixed(uint32_t w1, uint32_t w2, double& e, double& h)
+{
+    box_muller(w1, w2, e, h);
+}
+
 __device__ __forceinline__ float exp_r(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504089f); }
 __device__ __forceinline__ double exp_r(double x) { return exp(x); }
 __device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -152,35 +167,44 @@ __device__ __forceinline__ R pick(const R (&arr)[NM], int i)
 // ---------------------------------------------------------------------------
 // Andersen's quadratic-exponential step of one asset from (X, v) with the
 // correlated normal zx and the independent normal zv (constants c: QeP).  The
-// CIR conditional mean m and variance s^2 and the branch test psi <= 1.5 are
-// FP64 in both path precisions (the branch is a discrete choice; both sides
-// of a comparison with the oracle take it in FP64); the rest runs in R.
+// variance path -- its normal, its state and the whole step, including the
+// branch test psi <= 1.5 -- runs in FP64 in both path precisions: the two
+// branches map the same normal to different variances, so an FP32 variance
+// state that strays by rounding across psi = 1.5 would send the path off the
+// FP64 one for good.  The log price's drift K0 + K1 v + K2 v' is FP64 too
+// (K1 and K2 are near -rho/xi and rho/xi, so the sum cancels); its diffusion
+// term and the log price itself run in R.
 template <typename R, typename CP>
-__device__ __forceinline__ void qe_step(CP c, R zx, R zv, R& X, R& v)
+__device__ __forceinline__ void qe_step(CP c, R zx, double zv, R& X, double& v)
 {
-    const double vd = static_cast<double>(v);
-    const double m = c->mth + vd * c->E;
-    const double s2 = vd * c->c1 + c->c2;
-    R vn;
+    const double m = c->mth + v * c->E;
+    const double s2 = v * c->c1 + c->c2;
+    double vn;
     if (!(s2 > 0.0)) {
-        vn = static_cast<R>(m);
+        vn = m;
     } else {
         const double psi = s2 / (m * m);
-        const R ps = static_cast<R>(psi), mr = static_cast<R>(m);
         if (psi <= 1.5) {
-            const R t = div_r(R(2), ps);
-            const R b2 = t - R(1) + sqrt_r(t) * sqrt_r(t - R(1));
-            const R a = div_r(mr, R(1) + b2);
-            const R b = sqrt_r(b2);
+            const double t = 2.0 / psi;
+            const double b2 = t - 1.0 + sqrt(t) * sqrt(t - 1.0);
+            const double a = m / (1.0 + b2);
+            const double b = sqrt(b2);
             vn = a * (b + zv) * (b + zv);
         } else {
-            const R pm = div_r(ps - R(1), ps + R(1));
-            const R beta = div_r(R(1) - pm, mr);
-            const R u = ncdf_r(zv);
-            vn = u <= pm ? R(0) : div_r(log_r(div_r(R(1) - pm, R(1) - u)), beta);
+            const double pm = (psi - 1.0) / (psi + 1.0);
+            const double beta = (1.0 - pm) / m;
+            const double u = ncdf_r(zv);
+            vn = u <= pm ? 0.0 : log((1.0 - pm) / (1.0 - u)) / beta;
         }
     }
-    X = X + c->K0 + c->K1 * v + c->K2 * vn + sqrt_r(c->K3 * v + c->K4 * vn) * zx;
+    if constexpr (sizeof(R) == 8) {
+        X = X + c->K0 + c->K1 * v + c->K2 * vn + sqrt(c->K3 * v + c->K4 * vn) * zx;
+    } else {
+        // drift in FP64 (K1 v + K2 v' nearly cancels), diffusion in R
+        const double drift = c->K0 + c->K1 * v + c->K2 * vn;
+        X = X + static_cast<R>(drift) +
+            sqrt_r(static_cast<R>(c->K3 * v + c->K4 * vn)) * zx;
+    }
     v = vn;
 }
 
@@ -191,13 +215,16 @@ __device__ __forceinline__ void qe_step(CP c, R zx, R zv, R& X, R& v)
 // 64 * blockIdx.x + l.  blockIdx.y selects a "block group": W groups (one per
 // wave) of tasks.  LDS holds, double-buffered by step parity, the step's
 // normals (eps, eta), the base scenario's correlated normals Z^S, exp(X) and
-// max(v, 0), each [asset][lane].
-template <typename R, int NMAX, int TMAX, int SCHEME>
+// max(v, 0), each [asset][lane]; under QE the variance normal eta and the
+// variance state are FP64 (VT) in both path precisions.
+template <typename R, int NMAX, int TMAX, int SCHEME, typename FT>
 __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 {
+    using VT = std::conditional_t<SCHEME == HS_SCHEME_QE, double, R>;
     extern __shared__ unsigned char hs_smem[];
     constexpr int SLAB = NMAX * kLanes;  // one [asset][lane] array
     R* const lds = reinterpret_cast<R*>(hs_smem);
+    VT* const lds_eta = reinterpret_cast<VT*>(hs_smem + 2 * 5 * SLAB * sizeof(R));
 
     const int lane = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -219,29 +246,34 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
     const R half = R(0.5);
     const uint32_t plo = static_cast<uint32_t>(p);
     const uint32_t phi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32);
-    R2<R>* __restrict__ feat = static_cast<R2<R>*>(A.feat);
+    R2<FT>* __restrict__ feat = static_cast<R2<FT>*>(A.feat);
     const int64_t P = A.P;
     const int nblk = (N + 1) / 2;
 
     // base assets owned by this wave: a = w + i W
-    R Xo[kOwnPerWave], Vo[kOwnPerWave];
+    R Xo[kOwnPerWave];
+    VT Vo[kOwnPerWave];
 #pragma unroll
     for (int i = 0; i < kOwnPerWave; ++i) {
         const int a = w + i * W;
         Xo[i] = R(0);
-        Vo[i] = (a < N) ? bp->a[a].v0 : R(0);
+        Vo[i] = (a < N) ? static_cast<VT>(SCHEME == HS_SCHEME_QE ? bp->a[a].qe.v0 : bp->a[a].v0)
+                        : VT(0);
     }
-    R tX[TMAX], tV[TMAX];
+    R tX[TMAX];
+    VT tV[TMAX];
 #pragma unroll
     for (int t = 0; t < TMAX; ++t) {
         tX[t] = R(0);
-        tV[t] = (t < ntask) ? tk[t].v0 : R(0);
+        tV[t] = (t < ntask) ? static_cast<VT>(SCHEME == HS_SCHEME_QE ? tk[t].qe.v0 : tk[t].v0)
+                            : VT(0);
     }
 
     for (int k = 0; k < A.n; ++k) {
         R* const buf = lds + (k & 1) * 5 * SLAB;
         R* const s_eps = buf;
-        R* const s_eta = buf + SLAB;
+        VT* const s_eta = SCHEME == HS_SCHEME_QE ? lds_eta + (k & 1) * SLAB
+                                                 : reinterpret_cast<VT*>(buf + SLAB);
         R* const s_zs = buf + 2 * SLAB;
         R* const s_e = buf + 3 * SLAB;
         R* const s_vp = buf + 4 * SLAB;
@@ -250,12 +282,19 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
         for (int j = w; j < nblk; j += W) {
             const Words q = philox10(plo, static_cast<uint32_t>(k), static_cast<uint32_t>(j), phi,
                                      A.key0, A.key1);
-            R e, h;
-            box_muller(q.x, q.y, e, h);
+            R e;
+            VT h;
+            if constexpr (SCHEME == HS_SCHEME_QE)
+                box_muller_mixed(q.x, q.y, e, h);
+            else
+                box_muller(q.x, q.y, e, h);
             s_eps[(2 * j) * kLanes + lane] = e;
             s_eta[(2 * j) * kLanes + lane] = h;
             if (2 * j + 1 < N) {
-                box_muller(q.z, q.w, e, h);
+                if constexpr (SCHEME == HS_SCHEME_QE)
+                    box_muller_mixed(q.z, q.w, e, h);
+                else
+                    box_muller(q.z, q.w, e, h);
                 s_eps[(2 * j + 1) * kLanes + lane] = e;
                 s_eta[(2 * j + 1) * kLanes + lane] = h;
             }
@@ -281,7 +320,7 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                 }
                 s_zs[a * kLanes + lane] = z;
                 s_e[a * kLanes + lane] = exp_r(Xo[i]);
-                s_vp[a * kLanes + lane] = Vo[i] > R(0) ? Vo[i] : R(0);
+                s_vp[a * kLanes + lane] = static_cast<R>(Vo[i] > VT(0) ? Vo[i] : VT(0));
             }
         }
         __syncthreads();
@@ -322,9 +361,9 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 
         if (store && live) {
             if (g_base >= 0) {
-                R2<R> f;
-                f.u = sm[0];
-                f.a = bA;
+                R2<FT> f;
+                f.u = static_cast<FT>(sm[0]);
+                f.a = static_cast<FT>(bA);
                 feat[g_base * A.plane + off] = f;
             }
             if (g_up0 >= 0) {
@@ -336,11 +375,11 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                         const R ex = lo > hi ? lo : hi;
                         const R su = bp->S0_up[a] * E[a];
                         const R sd = bp->S0_dn[a] * E[a];
-                        R2<R> f;
-                        f.a = bA;
-                        f.u = su > ex ? su : ex;
+                        R2<FT> f;
+                        f.a = static_cast<FT>(bA);
+                        f.u = static_cast<FT>(su > ex ? su : ex);
                         feat[(g_up0 + a) * A.plane + off] = f;
-                        f.u = sd > ex ? sd : ex;
+                        f.u = static_cast<FT>(sd > ex ? sd : ex);
                         feat[(g_dn0 + a) * A.plane + off] = f;
                     }
                 }
@@ -372,7 +411,7 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                     tV[t] = tV[t] + T->kappa * (T->theta - vp) * T->dt + T->xi * sq * zv;
                 }
                 const R S = T->S0 * exp_r(tX[t]);
-                const R vpt = tV[t] > R(0) ? tV[t] : R(0);
+                const R vpt = static_cast<R>(tV[t] > VT(0) ? tV[t] : VT(0));
                 if (T->first) {
                     runM = T->lo > 0 ? pick(pm, T->lo - 1) : R(0);
                     runS = T->lo > 0 ? pick(ps, T->lo - 1) : R(0);
@@ -386,9 +425,9 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                         runS = runS + (bsum - pick(ps, T->hi - 1));
                     }
                     if (store && live) {
-                        R2<R> f;
-                        f.u = runM;
-                        f.a = runS * invN;
+                        R2<FT> f;
+                        f.u = static_cast<FT>(runM);
+                        f.a = static_cast<FT>(runS * invN);
                         feat[T->scen * A.plane + off] = f;
                     }
                 }
@@ -950,7 +989,7 @@ __device__ __forceinline__ bool cluster_exchange(double (&b)[K], int m, double* 
 // than one workgroup per CU can hold.  Both give the same numbers.
 template <typename R, int Q, bool KEEP>
 __global__ void __launch_bounds__(kClusterThreads,
-                                  (!KEEP && Q <= cluster_qmax_shared(sizeof(R) == 4)) ? 4 : 2)
+                                  (!KEEP && Q <= cluster_qmax_shared(sizeof(R) <= 4)) ? 4 : 2)
     k_sweep_cluster(const LsmcArgs A,
                                                                    const ClusterArgs C)
 {
@@ -1258,38 +1297,52 @@ __global__ void k_normals(uint32_t k0, uint32_t k1, int N, int64_t P, int n, R* 
     }
 }
 
-template <typename R, int NMAX, int TMAX, int SCHEME>
+template <typename R, int NMAX, int TMAX, int SCHEME, typename FT>
 hipError_t launch_paths_t(const PathArgs& a, int nchunks, int nbg, hipStream_t st)
 {
-    const size_t lds = 2u * 5u * NMAX * kLanes * sizeof(R);
+    const size_t lds = 2u * 5u * NMAX * kLanes * sizeof(R) +
+                       (SCHEME == HS_SCHEME_QE ? 2u * NMAX * kLanes * sizeof(double) : 0u);
     if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_paths<R, NMAX, TMAX, SCHEME>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_paths<R, NMAX, TMAX, SCHEME, FT>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
     dim3 grid(nchunks, nbg), block(kLanes, a.W);
-    hipLaunchKernelGGL((k_paths<R, NMAX, TMAX, SCHEME>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((k_paths<R, NMAX, TMAX, SCHEME, FT>), grid, block, lds, st, a);
     return hipGetLastError();
 }
 
-template <typename R, int SCHEME>
+template <typename R, int SCHEME, typename FT>
 hipError_t launch_paths_r(int nmax, const PathArgs& a, int nchunks, int nbg, hipStream_t st)
 {
     constexpr bool F = sizeof(R) == 4;
     switch (nmax) {
-    case 1: return launch_paths_t<R, 1, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 2: return launch_paths_t<R, 2, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 3: return launch_paths_t<R, 3, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 4: return launch_paths_t<R, 4, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 5: return launch_paths_t<R, 5, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 6: return launch_paths_t<R, 6, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 8: return launch_paths_t<R, 8, F ? 32 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 10: return launch_paths_t<R, 10, F ? 24 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 12: return launch_paths_t<R, 12, F ? 24 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 16: return launch_paths_t<R, 16, F ? 20 : 16, SCHEME>(a, nchunks, nbg, st);
-    case 20: return launch_paths_t<R, 20, 20, SCHEME>(a, nchunks, nbg, st);
+    case 1: return launch_paths_t<R, 1, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 2: return launch_paths_t<R, 2, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 3: return launch_paths_t<R, 3, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 4: return launch_paths_t<R, 4, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 5: return launch_paths_t<R, 5, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 6: return launch_paths_t<R, 6, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 8: return launch_paths_t<R, 8, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 10: return launch_paths_t<R, 10, F ? 24 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 12: return launch_paths_t<R, 12, F ? 24 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 16: return launch_paths_t<R, 16, F ? 20 : 16, SCHEME, FT>(a, nchunks, nbg, st);
+    case 20: return launch_paths_t<R, 20, 20, SCHEME, FT>(a, nchunks, nbg, st);
     default: return hipErrorInvalidValue;
+    }
+}
+
+// Calls f with a null pointer of the feature storage type of code ft.
+template <typename Ret, typename Fn>
+Ret with_feat(int ft, Ret bad, Fn&& f)
+{
+    switch (ft) {
+    case kFeatF32: return f(static_cast<float*>(nullptr));
+    case kFeatF64: return f(static_cast<double*>(nullptr));
+    case kFeatF16: return f(static_cast<_Float16*>(nullptr));
+    case kFeatBF16: return f(static_cast<__bf16*>(nullptr));
+    default: return bad;
     }
 }
 
@@ -1356,37 +1409,38 @@ size_t cluster_lds_bytes(int n, int G)
     return sizeof(double) * (2 * (kClusterThreads / 64) * kPartStride + 2 * kPartStride) + 16;
 }
 
-int cluster_capacity(bool fp32, int q, bool keep, size_t lds)
+int cluster_capacity(int ft, int q, bool keep, size_t lds)
 {
-    switch (q) {
+    return with_feat(ft, 0, [&](auto tag) -> int {
+        using FT = std::remove_pointer_t<decltype(tag)>;
+        switch (q) {
 #define HS_CAP(Q)                                                                        \
     case Q:                                                                              \
-        return fp32 ? (keep ? cluster_capacity_t<float, Q, true>(lds)                    \
-                            : cluster_capacity_t<float, Q, false>(lds))                  \
-                    : (keep ? cluster_capacity_t<double, Q, true>(lds)                   \
-                            : cluster_capacity_t<double, Q, false>(lds));
-        HS_CAP(1) HS_CAP(2) HS_CAP(3) HS_CAP(4) HS_CAP(5) HS_CAP(6) HS_CAP(7) HS_CAP(8)
+        return keep ? cluster_capacity_t<FT, Q, true>(lds) : cluster_capacity_t<FT, Q, false>(lds);
+            HS_CAP(1) HS_CAP(2) HS_CAP(3) HS_CAP(4) HS_CAP(5) HS_CAP(6) HS_CAP(7) HS_CAP(8)
 #undef HS_CAP
-    default: return 0;
-    }
+        default: return 0;
+        }
+    });
 }
 
-hipError_t launch_sweep_cluster(bool fp32, int q, bool keep, const LsmcArgs& a,
+hipError_t launch_sweep_cluster(int ft, int q, bool keep, const LsmcArgs& a,
                                 const ClusterArgs& c, int S_launch, hipStream_t st)
 {
     const size_t lds = cluster_lds_bytes(a.n, c.G);
-    switch (q) {
-#define HS_LAUNCH(Q)                                                                    \
-    case Q:                                                                             \
-        return fp32 ? (keep ? launch_cluster_t<float, Q, true>(a, c, S_launch, lds, st)  \
-                            : launch_cluster_t<float, Q, false>(a, c, S_launch, lds, st)) \
-                    : (keep ? launch_cluster_t<double, Q, true>(a, c, S_launch, lds, st) \
-                            : launch_cluster_t<double, Q, false>(a, c, S_launch, lds, st));
-        HS_LAUNCH(1) HS_LAUNCH(2) HS_LAUNCH(3) HS_LAUNCH(4) HS_LAUNCH(5) HS_LAUNCH(6) HS_LAUNCH(7)
-        HS_LAUNCH(8)
+    return with_feat(ft, hipErrorInvalidValue, [&](auto tag) -> hipError_t {
+        using FT = std::remove_pointer_t<decltype(tag)>;
+        switch (q) {
+#define HS_LAUNCH(Q)                                                             \
+    case Q:                                                                      \
+        return keep ? launch_cluster_t<FT, Q, true>(a, c, S_launch, lds, st)     \
+                    : launch_cluster_t<FT, Q, false>(a, c, S_launch, lds, st);
+            HS_LAUNCH(1) HS_LAUNCH(2) HS_LAUNCH(3) HS_LAUNCH(4) HS_LAUNCH(5) HS_LAUNCH(6)
+            HS_LAUNCH(7) HS_LAUNCH(8)
 #undef HS_LAUNCH
-    default: return hipErrorInvalidValue;
-    }
+        default: return hipErrorInvalidValue;
+        }
+    });
 }
 
 hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st)
@@ -1417,14 +1471,27 @@ size_t paths_lds_bytes(bool fp32, int nmax)
     return 2u * 5u * static_cast<size_t>(nmax) * kLanes * (fp32 ? 4u : 8u);
 }
 
-hipError_t launch_paths(bool fp32, int nmax, int scheme, const PathArgs& a, int nchunks, int nbg,
-                        hipStream_t st)
+hipError_t launch_paths(bool fp32, int nmax, int scheme, int ft, const PathArgs& a, int nchunks,
+                        int nbg, hipStream_t st)
 {
+    if (!fp32) {
+        if (ft != kFeatF64) return hipErrorInvalidValue;
+        return scheme == HS_SCHEME_QE
+                   ? launch_paths_r<double, HS_SCHEME_QE, double>(nmax, a, nchunks, nbg, st)
+                   : launch_paths_r<double, HS_SCHEME_EULER_FT, double>(nmax, a, nchunks, nbg, st);
+    }
     if (scheme == HS_SCHEME_QE)
-        return fp32 ? launch_paths_r<float, HS_SCHEME_QE>(nmax, a, nchunks, nbg, st)
-                    : launch_paths_r<double, HS_SCHEME_QE>(nmax, a, nchunks, nbg, st);
-    return fp32 ? launch_paths_r<float, HS_SCHEME_EULER_FT>(nmax, a, nchunks, nbg, st)
-                : launch_paths_r<double, HS_SCHEME_EULER_FT>(nmax, a, nchunks, nbg, st);
+        return ft == kFeatF32 ? launch_paths_r<float, HS_SCHEME_QE, float>(nmax, a, nchunks, nbg, st)
+                              : hipErrorInvalidValue;
+    switch (ft) {
+    case kFeatF32:
+        return launch_paths_r<float, HS_SCHEME_EULER_FT, float>(nmax, a, nchunks, nbg, st);
+    case kFeatF16:
+        return launch_paths_r<float, HS_SCHEME_EULER_FT, _Float16>(nmax, a, nchunks, nbg, st);
+    case kFeatBF16:
+        return launch_paths_r<float, HS_SCHEME_EULER_FT, __bf16>(nmax, a, nchunks, nbg, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename R>
@@ -1434,10 +1501,12 @@ hipError_t launch_gram_r(const LsmcArgs& a, int S, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_gram(bool fp32, const LsmcArgs& a, int S, hipStream_t st)
+hipError_t launch_gram(int ft, const LsmcArgs& a, int S, hipStream_t st)
 {
     if (a.n < 2) return hipSuccess;
-    return fp32 ? launch_gram_r<float>(a, S, st) : launch_gram_r<double>(a, S, st);
+    return with_feat(ft, hipErrorInvalidValue, [&](auto tag) {
+        return launch_gram_r<std::remove_pointer_t<decltype(tag)>>(a, S, st);
+    });
 }
 
 int sweep_q_for(int64_t P)
@@ -1448,9 +1517,11 @@ int sweep_q_for(int64_t P)
     return 0;  // state in the workspace
 }
 
-hipError_t launch_sweep(bool fp32, int q, const LsmcArgs& a, int S, hipStream_t st)
+hipError_t launch_sweep(int ft, int q, const LsmcArgs& a, int S, hipStream_t st)
 {
-    return fp32 ? launch_sweep_r<float>(q, a, S, st) : launch_sweep_r<double>(q, a, S, st);
+    return with_feat(ft, hipErrorInvalidValue, [&](auto tag) {
+        return launch_sweep_r<std::remove_pointer_t<decltype(tag)>>(q, a, S, st);
+    });
 }
 
 hipError_t launch_philox_words(uint64_t seed, int64_t P, int n, int nb, uint32_t* out,

@@ -14,24 +14,28 @@ namespace hs {
 int paths_nmax_bucket(int N);
 int paths_tmax(bool fp32, int nmax);
 size_t paths_lds_bytes(bool fp32, int nmax);
-hipError_t launch_paths(bool fp32, int nmax, int scheme, const PathArgs& a, int nchunks,
+hipError_t launch_paths(bool fp32, int nmax, int scheme, int feat, const PathArgs& a, int nchunks,
                         int nblockgroups, hipStream_t st);
 
+// The kernels after the path kernel are compiled per feature storage type
+// (FeatType: FP32, FP64, FP16, BF16), the path kernel per path precision,
+// scheme and storage type.
+
 // Gram matrices and their Cholesky factors for dates 1..n-1 of S scenarios.
-hipError_t launch_gram(bool fp32, const LsmcArgs& a, int S, hipStream_t st);
+hipError_t launch_gram(int feat, const LsmcArgs& a, int S, hipStream_t st);
 
 // Backward sweep + price of S scenarios.  q = paths per thread with the state
 // in registers (1,2,4,8,16), or 0 for the state in the workspace.
 int sweep_q_for(int64_t P);
-hipError_t launch_sweep(bool fp32, int q, const LsmcArgs& a, int S, hipStream_t st);
+hipError_t launch_sweep(int feat, int q, const LsmcArgs& a, int S, hipStream_t st);
 
 // Cluster sweep: Q in 1..8 paths per thread, G workgroups per scenario,
 // S_launch scenarios (planes c.s0 ..) per launch; keep = each path keeps its
 // basis values between a date's regression and its decision (more registers);
 // capacity = workgroups that fit on the device at once.
 size_t cluster_lds_bytes(int n, int G);
-int cluster_capacity(bool fp32, int q, bool keep, size_t lds);
-hipError_t launch_sweep_cluster(bool fp32, int q, bool keep, const LsmcArgs& a,
+int cluster_capacity(int feat, int q, bool keep, size_t lds);
+hipError_t launch_sweep_cluster(int feat, int q, bool keep, const LsmcArgs& a,
                                 const ClusterArgs& c, int S_launch, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st);
 

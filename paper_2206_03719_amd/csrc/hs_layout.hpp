@@ -16,15 +16,19 @@ constexpr int kGramThreads = 256; // Gram kernel block
 constexpr int kSweepThreads = 1024;
 constexpr int kRegRec = 20;       // doubles per (scenario, date) regression record
 
+// Storage type of the path features (U, A) in the workspace.
+enum FeatType { kFeatF32 = 0, kFeatF64 = 1, kFeatF16 = 2, kFeatBF16 = 3 };
+constexpr size_t feat_bytes(int ft) { return ft == kFeatF64 ? 16 : ft == kFeatF32 ? 8 : 4; }
+
 // Quadratic-exponential step constants of one asset of one scenario (host
 // FP64): E = exp(-kappa dt), mth = theta (1 - E), c1, c2 with the CIR
-// conditional variance s^2 = v c1 + c2, and the log-price coefficients
-// K0 (with r dt), K1..K4.  The branch test psi = s^2/m^2 <= 1.5 runs in FP64
-// in both path precisions.
+// conditional variance s^2 = v c1 + c2, the initial variance v0, and the
+// log-price coefficients K0 (with r dt), K1..K4.  All FP64: the variance path
+// and the log-price drift run in FP64 in both path precisions (K1 and K2 are
+// near -rho/xi and +rho/xi, and their FP32 roundings would not cancel).
 template <typename R>
 struct QeP {
-    double E, mth, c1, c2;
-    R K0, K1, K2, K3, K4, pad[3];
+    double E, mth, c1, c2, v0, K0, K1, K2, K3, K4;
 };
 
 // One asset of the base scenario.  rhobar = sqrt(1 - rho^2) (host FP64).

@@ -247,13 +247,22 @@ hs_status validate(const Request& q)
         set_error("opts.sweep_mode = 1 needs n_paths <= %d", 16 * kSweepThreads);
         return HS_EINVAL;
     }
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (op.reserved[i] != 0) {
             set_error("opts.reserved must be zero");
             return HS_EINVAL;
         }
     if (op.scheme != HS_SCHEME_EULER_FT && op.scheme != HS_SCHEME_QE) {
         set_error("opts.scheme = %d", op.scheme);
+        return HS_EINVAL;
+    }
+    if (op.feature_format < HS_FEATURES_NATIVE || op.feature_format > HS_FEATURES_BF16) {
+        set_error("opts.feature_format = %d", op.feature_format);
+        return HS_EINVAL;
+    }
+    if (op.feature_format != HS_FEATURES_NATIVE &&
+        (op.precision != HS_FP32_PATHS || op.scheme != HS_SCHEME_EULER_FT)) {
+        set_error("16-bit feature storage needs FP32 paths and the Euler scheme");
         return HS_EINVAL;
     }
     if (op.scheme == HS_SCHEME_QE)
@@ -367,6 +376,10 @@ Shape shape_of(const Request& q)
     sh.american = q.opt.style == HS_AMERICAN;
     sh.nmax = paths_nmax_bucket(q.N);
     sh.tmax = paths_tmax(sh.fp32, sh.nmax);
+    sh.feat = !sh.fp32 ? kFeatF64
+              : q.opts.feature_format == HS_FEATURES_FP16 ? kFeatF16
+              : q.opts.feature_format == HS_FEATURES_BF16 ? kFeatBF16
+                                                          : kFeatF32;
     // cluster sweep shape from the request alone (never from device load, nor
     // from the workspace): spread the Greek set's scenarios over the compute
     // units, from one path per thread up to 8
@@ -434,7 +447,7 @@ Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, in
         off = align_up(off + S * cluster_rows(sh.american, q.n) *
                                  static_cast<size_t>(sh.cluster_g) * kPartStride * sizeof(double));
     L.feat = off;
-    off = align_up(off + S * nd * P * 2 * R);
+    off = align_up(off + S * nd * P * feat_bytes(sh.feat));
     L.total = off;
     return L;
 }
@@ -447,7 +460,7 @@ namespace {
 // coefficients, with rho/xi read as 0 when xi = 0 (validation then demands
 // rho = 0).
 template <typename R>
-QeP<R> qe_params(double kappa, double theta, double xi, double rho, double r, double dt)
+QeP<R> qe_params(double v0, double kappa, double theta, double xi, double rho, double r, double dt)
 {
     QeP<R> c;
     std::memset(&c, 0, sizeof c);
@@ -455,14 +468,15 @@ QeP<R> qe_params(double kappa, double theta, double xi, double rho, double r, do
     const double f = kappa > 0.0 ? -std::expm1(-kappa * dt) / kappa : dt;  // (1 - E)/kappa
     const double rx = xi > 0.0 ? rho / xi : 0.0;
     c.E = E;
+    c.v0 = v0;
     c.mth = theta * (1.0 - E);
     c.c1 = xi * xi * E * f;
     c.c2 = 0.5 * theta * xi * xi * (1.0 - E) * f;
-    c.K0 = static_cast<R>(r * dt - rx * kappa * theta * dt);
-    c.K1 = static_cast<R>(0.5 * dt * (kappa * rx - 0.5) - rx);
-    c.K2 = static_cast<R>(0.5 * dt * (kappa * rx - 0.5) + rx);
-    c.K3 = static_cast<R>(0.5 * dt * (1.0 - rho * rho));
-    c.K4 = static_cast<R>(0.5 * dt * (1.0 - rho * rho));
+    c.K0 = r * dt - rx * kappa * theta * dt;
+    c.K1 = 0.5 * dt * (kappa * rx - 0.5) - rx;
+    c.K2 = 0.5 * dt * (kappa * rx - 0.5) + rx;
+    c.K3 = 0.5 * dt * (1.0 - rho * rho);
+    c.K4 = 0.5 * dt * (1.0 - rho * rho);
     return c;
 }
 
@@ -482,7 +496,7 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
         bp.a[a].xi = static_cast<R>(q.xi[a]);
         bp.a[a].rho = static_cast<R>(q.rho[a]);
         bp.a[a].rhobar = static_cast<R>(std::sqrt(1.0 - q.rho[a] * q.rho[a]));
-        bp.a[a].qe = qe_params<R>(q.kappa[a], q.theta[a], q.xi[a], q.rho[a], q.r,
+        bp.a[a].qe = qe_params<R>(q.v0[a], q.kappa[a], q.theta[a], q.xi[a], q.rho[a], q.r,
                                   q.opt.T / static_cast<double>(q.n));
         for (int c = 0; c < N; ++c) bp.L[a * kMaxAssets + c] = static_cast<R>(b0.L[a * N + c]);
         bp.S0_up[a] = static_cast<R>(q.S0[a] * (1.0 + q.bumps.spot_rel));
@@ -533,7 +547,7 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
                 t.rhobar = static_cast<R>(std::sqrt(1.0 - q.rho[a] * q.rho[a]));
                 t.r = static_cast<R>(s.r);
                 t.dt = static_cast<R>(s.T / static_cast<double>(q.n));
-                t.qe = qe_params<R>(q.kappa[a], q.theta[a], q.xi[a], q.rho[a], s.r,
+                t.qe = qe_params<R>(s.v0[a], q.kappa[a], q.theta[a], q.xi[a], q.rho[a], s.r,
                                     s.T / static_cast<double>(q.n));
                 for (int c = 0; c < N; ++c) t.L[c] = static_cast<R>(s.L[a * N + c]);
                 tasks.push_back(t);

@@ -65,6 +65,7 @@ struct Shape {
     bool fp32 = true;
     bool american = true;
     int nmax = 0, tmax = 0;
+    int feat = kFeatF32;    // FeatType of the stored features
     int sweep = kSweepCluster;
     int sweep_q = 0;        // single-workgroup sweep: paths per thread (0 = state in workspace)
     int cluster_q = 0;      // cluster sweep: paths per thread

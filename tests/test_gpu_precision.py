@@ -1,0 +1,84 @@
+"""Precision x time-step study (the paper's numeric-representation experiment,
+Sec. 4.2 and its Table 4, for this path): the 5-asset best-of American call,
+25,000 paths, price and spot Greeks (base and spot-bumped scenarios) at 126,
+252, 504, 1260 and 2520 steps, with FP64 paths, FP32 paths, and FP32 paths
+whose features are stored in FP16 or BF16, for the Euler and QE schemes;
+percentage deviation from the FP64 oracle on the same Philox streams.  The
+table goes to gpurun_out/precision_timestep_study.json.
+
+Exactness of the storage itself: the FP16 / BF16 features are the FP32
+features rounded to nearest-even."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+hs = None
+
+
+def setup_module(module):
+    global hs
+    import paper_2206_03719_amd as _hs
+    hs = _hs
+    hs.lib()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("features", ["fp16", "bf16"])
+def test_feature_storage_is_round_to_nearest(features):
+    import torch
+    w = W.best_of_call(n_assets=5, n_paths=777, n_steps=64)
+    f32 = hs.path_features(w["model"], w["corr"], 1.0, 777, 64, seed=42, precision="fp32")
+    f16 = hs.path_features(w["model"], w["corr"], 1.0, 777, 64, seed=42, precision="fp32",
+                           features=features)
+    want = f32.to(torch.float16 if features == "fp16" else torch.bfloat16)
+    assert f16.dtype == want.dtype
+    assert torch.equal(f16.view(torch.int16), want.view(torch.int16))
+
+
+STEPS = (126, 252, 504, 1260, 2520)
+VARIANTS = [("euler", "fp64", "native"), ("euler", "fp32", "native"), ("euler", "fp32", "fp16"),
+            ("euler", "fp32", "bf16"), ("qe", "fp64", "native"), ("qe", "fp32", "native")]
+# bars on the worst percentage deviation of the price and of delta_0
+BARS = {"fp64": (1e-10, 1e-6), "fp32": (1e-2, 1e-1), "fp16": (1.0, 10.0), "bf16": (10.0, 100.0)}
+
+
+def test_precision_timestep_study():
+    P = 25000
+    rows = []
+    for n in STEPS:
+        w = W.best_of_call(n_assets=5, n_paths=P, n_steps=n, mask=1)  # base + spot bumps
+        ref = {}
+        for scheme in ("euler", "qe"):
+            o = oracle.price_greeks(w["model"], w["corr"], w["option"], P, n, w["bumps"],
+                                    w["seed"], scheme=scheme)
+            ref[scheme] = (o["price"], o["delta"][0])
+        for scheme, prec, feat in VARIANTS:
+            g = hs.price_greeks(w["model"], w["corr"], w["option"], P, n, w["bumps"],
+                                seed=w["seed"], precision=prec, scheme=scheme, features=feat)
+            p0, d0 = ref[scheme]
+            row = {"steps": n, "scheme": scheme, "paths": prec, "features": feat,
+                   "price": g["price"], "price_dev_pct": 100 * abs(g["price"] - p0) / abs(p0),
+                   "delta0": g["delta"][0], "delta0_dev_pct": 100 * abs(g["delta"][0] - d0) / abs(d0)}
+            rows.append(row)
+            _say("  n=%4d %-5s %-4s %-6s price dev %.2e %%  delta0 dev %.2e %%"
+                 % (n, scheme, prec, feat, row["price_dev_pct"], row["delta0_dev_pct"]))
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "precision_timestep_study.json"), "w") as f:
+        json.dump(rows, f, indent=1)
+    for r in rows:
+        key = r["features"] if r["features"] != "native" else r["paths"]
+        bp, bd = BARS[key]
+        assert r["price_dev_pct"] <= bp, r
+        assert r["delta0_dev_pct"] <= bd, r
