@@ -136,6 +136,11 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
+    ap.add_argument("--table1", action="store_true",
+                    help="instead of the Greek set: the paper's Table 1 problem sizes through "
+                         "the base-model path kernel, one JSON line per size and variant")
+    ap.add_argument("--table1-sizes", default="tiny,small,medium,large,huge")
+    ap.add_argument("--table1-variants", default="fp32:euler,fp64:euler,fp32:qe,fp64:qe")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -154,6 +159,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copied 1 GiB 5 times")
+        return
+    if args.table1:
+        table1_leg(hs, torch, args)
         return
     w = W.best_of_call(n_assets=5, n_paths=25000, n_steps=252, precision="fp32")
     N, P, n = 5, w["n_paths"], w["n_steps"]
@@ -292,6 +300,89 @@ def main():
         log("serving: %s" % json.dumps(out["latency"]))
 
     print(json.dumps(out), flush=True)
+
+
+# The paper's multi-kernel runtimes (its Table A1: Heston paths plus the path
+# reduction, FPGA and two 24-core CPUs, float and double), in ms.
+PAPER_TA1_MS = {
+    ("tiny", "float"): (46.11, 372.15), ("tiny", "double"): (75.97, 369.07),
+    ("small", "float"): (82.01, 629.18), ("small", "double"): (141.39, 638.67),
+    ("medium", "float"): (341.82, 1545.94), ("medium", "double"): (592.79, 1551.90),
+    ("large", "float"): (1178.14, 4574.41), ("large", "double"): (1971.64, 4558.11),
+    ("huge", "float"): (5838.23, 15825.42), ("huge", "double"): (10644.86, 15561.09),
+}
+
+
+def base_kernel_slots(N, P, n):
+    """Algorithmic VALU slots of the base-model path kernel, FP32 Euler: per
+    element the random numbers (about 70 slots, see path_kernel_slots) and one
+    Euler step with its correlation row (25 + (N+1)/2 slots)."""
+    return (70.0 + 25.0 + (N + 1) / 2.0) * N * P * n
+
+
+def table1_leg(hs, torch, args):
+    """The paper's Table 1 problem sizes (assets x daily steps x 25k paths)
+    through hs_path_features: Heston paths and the per-date path reduction,
+    the stage the paper times.  Device time of each call (model upload and
+    kernel) from HIP events on the call's stream; elements = assets x steps x
+    paths.  The FP64 oracle runs the same work on the host cores for the
+    smallest size on a bounded sample of paths."""
+    stream = torch.cuda.Stream()
+    sizes = [s for s in args.table1_sizes.split(",") if s]
+    variants = [tuple(v.split(":")) for v in args.table1_variants.split(",") if v]
+    for size in sizes:
+        w = W.paper_size(size)
+        N, n, P, T = w["n_assets"], w["n_steps"], w["n_paths"], w["T"]
+        elements = N * n * P
+        for prec, scheme in variants:
+            dt = torch.float32 if prec == "fp32" else torch.float64
+            out = torch.empty((n, P, 2), dtype=dt, device="cuda")
+
+            def call():
+                with torch.cuda.stream(stream):
+                    hs.path_features(w["model"], w["corr"], T, P, n, seed=w["seed"],
+                                     precision=prec, scheme=scheme, stream=stream, out=out)
+            for _ in range(max(1, args.warmup)):
+                call()
+            times = []
+            for _ in range(args.steps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                call()
+                e1.record(stream)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = float(np.median(times))
+            fpga_ms, cpu_ms = PAPER_TA1_MS[(size, "float" if prec == "fp32" else "double")]
+            line = {"table1": size, "n_assets": N, "n_steps": n, "n_paths": P, "T": T,
+                    "precision": prec, "scheme": scheme, "ms": round(ms, 4),
+                    "ms_min": round(float(np.min(times)), 4), "reps": args.steps,
+                    "elements": elements, "elements_per_s": elements / (ms * 1e-3),
+                    "paper_fpga_ms": fpga_ms, "paper_cpu_ms": cpu_ms,
+                    "paper_fpga_elements_per_s": elements / (fpga_ms * 1e-3),
+                    "x_paper_fpga": round(fpga_ms / ms, 1), "x_paper_cpu": round(cpu_ms / ms, 1)}
+            if prec == "fp32" and scheme == "euler":
+                slots = base_kernel_slots(N, P, n)
+                line["alu_frac"] = round(slots / (ms * 1e-3) / ALU_PEAK_OPS, 4)
+            log("%s %s %s: %.3f ms, %.3e elements/s (paper FPGA %.1f ms)"
+                % (size, prec, scheme, ms, elements / (ms * 1e-3), fpga_ms))
+            print(json.dumps(line), flush=True)
+            del out
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        w = W.paper_size("tiny", n_paths=5000)
+        N, n, P, T = w["n_assets"], w["n_steps"], w["n_paths"], w["T"]
+        for scheme in ("euler", "qe"):
+            t0 = time.perf_counter()
+            oracle.features(w["model"], w["corr"], T, n, P, w["seed"], nthreads=threads,
+                            scheme=scheme)
+            sec = time.perf_counter() - t0
+            print(json.dumps({"table1_cpu_baseline": "tiny", "scheme": scheme, "kind": "oracle",
+                              "sample": "the first 5,000 of the 25,000 paths",
+                              "elements_per_s": N * n * P / sec, "seconds": sec,
+                              "cores": threads, "cpu": cpu_model()}), flush=True)
 
 
 def cpu_model():

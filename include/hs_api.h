@@ -38,7 +38,8 @@ extern "C" {
 #endif
 
 #define HS_API_VERSION 1
-#define HS_MAX_ASSETS 20
+#define HS_MAX_ASSETS 20      /* Greek sets and serving requests               */
+#define HS_MAX_PATH_ASSETS 64 /* hs_path_features (the model alone)            */
 
 typedef int32_t hs_status;
 #define HS_OK 0
@@ -123,9 +124,14 @@ typedef int32_t hs_status;
 #define HS_FLAG_GRAPH 4u      /* run each pass as a hipGraph: captured once per
                                  launch shape and workspace, then replayed (needs a
                                  non-null stream; ignored with HS_FLAG_TIMING)      */
+#define HS_FLAG_GREEK_SET_KERNEL 8u /* hs_path_features only: compute the features
+                                 with the Greek-set path kernel that hs_price_greeks
+                                 runs (n_assets <= HS_MAX_ASSETS, waves_per_block
+                                 <= 8) instead of the base-model kernel; the two
+                                 give the same features bit for bit              */
 
 typedef struct hs_model {
-    int32_t n_assets;       /* 1..HS_MAX_ASSETS                                */
+    int32_t n_assets;       /* 1..HS_MAX_ASSETS (hs_path_features: ..64)       */
     const double *S0;       /* host, spot > 0                                  */
     const double *v0;       /* host, initial variance >= 0 (> 0 if VEGA)       */
     const double *kappa;    /* host, mean-reversion speed >= 0                 */
@@ -218,7 +224,7 @@ size_t hs_workspace_min_bytes(const hs_model *model, const hs_option *option, in
  * per-asset Heston configurations, assets x paths x timesteps in; per-asset
  * sensitivities out, Sec. 2.2.1).
  *   model, corr (host), option, bumps, opts: as documented above.
- *   n_paths in 2..2^40, n_steps in 1..4096 (dt = T / n_steps).
+ *   n_paths in 2..2^31, n_steps in 1..4096 (dt = T / n_steps).
  *   d_workspace: device, >= hs_workspace_min_bytes, 256-byte aligned.
  *   out: host struct; its arrays are caller-allocated (see hs_greeks).
  * Validation happens before any device work.  Errors: HS_EINVAL (ranges,
@@ -230,13 +236,25 @@ hs_status hs_price_greeks(const hs_model *model, const double *corr, const hs_op
                           const hs_opts *opts, void *d_workspace, size_t workspace_bytes,
                           void *hip_stream, hs_greeks *out);
 
-/* The paper's measured kernel on its own (Sec. 2.2.1 and 4.1): Heston paths
- * of the base model and, at each date k = 1..n_steps, the path reduction
- * U = max_i S_i and A = (1/N) sum_i max(v_i, 0).  Output d_out (device):
- * [n_steps][n_paths][2] of double (HS_FP64), float (HS_FP32_PATHS), or
- * half / bfloat16 with opts.feature_format FP16 / BF16.
- * d_workspace: device, >= hs_path_features_workspace_bytes.  Enqueued only;
- * the call does not synchronize. */
+/* The paper's measured kernel on its own (Sec. 2.2.1 and 4.1, the problem
+ * sizes of its Table 1): Heston paths of the base model and, at each date
+ * k = 1..n_steps, the path reduction U = max_i S_i and A = (1/N) sum_i
+ * max(v_i, 0), summed in asset order.
+ *   model: n_assets in 1..HS_MAX_PATH_ASSETS (1..HS_MAX_ASSETS with
+ *          HS_FLAG_GREEK_SET_KERNEL); corr, opts as for hs_price_greeks
+ *          (opts.waves_per_block 0 = auto, else 1..16: waves that share a
+ *          block of 64 paths, raised to ceil(ceil(n_assets / 2) / 8) if
+ *          smaller; never changes the result).  Only HS_FLAG_GREEK_SET_KERNEL
+ *          is accepted in opts.flags beyond the common flags, which are ignored.
+ *   n_paths in 2..2^31, n_steps in 1..4096, T > 0 (dt = T / n_steps).
+ *   d_out (device): [n_steps][n_paths][2] of double (HS_FP64), float
+ *          (HS_FP32_PATHS), or half / bfloat16 with opts.feature_format
+ *          FP16 / BF16; out_bytes must cover it (else HS_ENOMEM).
+ *   d_workspace (device, 256-byte aligned): >= hs_path_features_workspace_bytes,
+ *          which holds the model table the kernel reads.
+ * Validation as for hs_price_greeks (HS_EINVAL, HS_ENOTSPD) before any device
+ * work.  The work is enqueued on hip_stream and the call returns once that
+ * stream has drained: the output is complete on return. */
 size_t hs_path_features_workspace_bytes(int32_t n_assets);
 hs_status hs_path_features(const hs_model *model, const double *corr, int64_t n_paths,
                            int32_t n_steps, double T, const hs_opts *opts, void *d_out,

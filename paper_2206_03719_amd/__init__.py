@@ -21,7 +21,8 @@ SINGLE, MAX_OF = 0, 1
 BASIS_AUTO, BASIS_QUAD, BASIS_QUAD_VOL = 0, 1, 2
 BUMP_DELTA_GAMMA, BUMP_VEGA, BUMP_THETA, BUMP_RHO, BUMP_CORR, BUMP_ALL = 1, 2, 4, 8, 16, 31
 FP64, FP32_PATHS = 0, 1
-FLAG_EXPORT_TAU, FLAG_TIMING, FLAG_GRAPH = 1, 2, 4
+FLAG_EXPORT_TAU, FLAG_TIMING, FLAG_GRAPH, FLAG_GREEK_SET_KERNEL = 1, 2, 4, 8
+MAX_ASSETS, MAX_PATH_ASSETS = 20, 64
 SCHEME_EULER_FT, SCHEME_QE = 0, 1
 SCHEMES = {"euler": SCHEME_EULER_FT, "qe": SCHEME_QE}
 FEATURES_NATIVE, FEATURES_FP16, FEATURES_BF16 = 0, 1, 2
@@ -286,15 +287,25 @@ def autotune(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="f
 
 
 def path_features(model, corr, T, n_paths, n_steps, seed=42, precision="fp64", stream=None,
-                  scheme="euler", features="native"):
+                  scheme="euler", features="native", greek_set_kernel=False, waves_per_block=0,
+                  out=None):
     """Heston paths + per-date path reduction of the base model
-    (hs_path_features): a CUDA tensor [n_steps, n_paths, 2] of (U, A)."""
+    (hs_path_features): a CUDA tensor [n_steps, n_paths, 2] of (U, A).
+    greek_set_kernel: compute them with the Greek-set path kernel instead of
+    the base-model kernel (same result).  out: an existing tensor of that
+    shape and dtype to write into."""
     torch = _torch()
     m = _Marshal(model, corr, {"cp": "call", "style": "american", "K": 1.0, "T": T},
-                 None, seed, precision, scheme=scheme, features=features)
+                 None, seed, precision, scheme=scheme, features=features,
+                 flags=FLAG_GREEK_SET_KERNEL if greek_set_kernel else 0,
+                 waves_per_block=waves_per_block)
     dtype = {FEATURES_FP16: torch.float16, FEATURES_BF16: torch.bfloat16}.get(
         m.opts.feature_format, torch.float64 if m.opts.precision == FP64 else torch.float32)
-    out = torch.empty((n_steps, n_paths, 2), dtype=dtype, device="cuda")
+    if out is None:
+        out = torch.empty((n_steps, n_paths, 2), dtype=dtype, device="cuda")
+    elif out.dtype != dtype or tuple(out.shape) != (n_steps, n_paths, 2) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of shape %s"
+                         % (dtype, (n_steps, n_paths, 2)))
     wsb = int(lib().hs_path_features_workspace_bytes(m.N))
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     st = lib().hs_path_features(ctypes.byref(m.model), m.corr_ptr, int(n_paths), int(n_steps),

@@ -552,30 +552,38 @@ hs_status hs_autotune(const hs_model* model, const double* corr, const hs_option
 size_t hs_path_features_workspace_bytes(int32_t n_assets)
 {
     (void)n_assets;
-    return 2 * 256 + sizeof(BaseP<double>) + kMaxWaves * sizeof(GroupP);
+    const size_t greek_set = 2 * 256 + sizeof(BaseP<double>) + kMaxWaves * sizeof(GroupP);
+    return std::max(greek_set, sizeof(ModelP<double>));
 }
+
 
 hs_status hs_path_features(const hs_model* model, const double* corr, int64_t n_paths,
                            int32_t n_steps, double T, const hs_opts* opts, void* d_out,
                            size_t out_bytes, void* d_workspace, size_t workspace_bytes,
                            void* hip_stream)
 {
-    if (!d_out || !d_workspace) {
-        set_error("hs_path_features: null output or workspace");
+    if (!d_out || !d_workspace || !opts) {
+        set_error("hs_path_features: null output, workspace or opts");
         return HS_EINVAL;
     }
+    const bool greek_set = (opts->flags & HS_FLAG_GREEK_SET_KERNEL) != 0;
     hs_option opt{HS_CALL, HS_AMERICAN, HS_MAX_OF, HS_BASIS_AUTO, 1.0, T};
     hs_bumps nob{0u, 0.0, 0.0, 0.0, 0.0, 0.0};
     Request q;
-    hs_status rc = copy_request(model, corr, &opt, n_paths, n_steps, &nob, opts, q);
+    hs_status rc = copy_request(model, corr, &opt, n_paths, n_steps, &nob, opts, q,
+                                greek_set ? kMaxAssets : kMaxPathAssets);
     if (rc != HS_OK) return rc;
-    rc = validate(q);
+    rc = validate(q, greek_set ? kMaxWaves : kBaseMaxWaves, HS_FLAG_GREEK_SET_KERNEL);
     if (rc != HS_OK) return rc;
     std::vector<Scenario> sc;
     rc = expand_scenarios(q, sc);
     if (rc != HS_OK) return rc;
-    const Shape sh = shape_of(q);
-    const size_t need = static_cast<size_t>(n_steps) * n_paths * feat_bytes(sh.feat);
+    const bool fp32 = q.opts.precision == HS_FP32_PATHS;
+    const int ft = !fp32 ? kFeatF64
+                   : q.opts.feature_format == HS_FEATURES_FP16 ? kFeatF16
+                   : q.opts.feature_format == HS_FEATURES_BF16 ? kFeatBF16
+                                                               : kFeatF32;
+    const size_t need = static_cast<size_t>(n_steps) * n_paths * feat_bytes(ft);
     if (out_bytes < need) {
         set_error("hs_path_features: output needs %zu bytes, got %zu", need, out_bytes);
         return HS_ENOMEM;
@@ -585,12 +593,47 @@ hs_status hs_path_features(const hs_model* model, const double* corr, int64_t n_
                   hs_path_features_workspace_bytes(q.N));
         return HS_ENOMEM;
     }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    unsigned char* ws = static_cast<unsigned char*>(d_workspace);
+    if (!greek_set) {
+        // waves: as asked (auto: one per Philox block, up to 16), then the
+        // nearest count the kernel supports for this asset count, upwards
+        // first (at most four blocks per wave; fewer waves where the variant
+        // needs more registers)
+        const int nblk = (q.N + 1) / 2;
+        const int want =
+            q.opts.waves_per_block > 0 ? q.opts.waves_per_block : std::min(kBaseMaxWaves, nblk);
+        int W = -1;
+        for (int c = want; c <= kBaseMaxWaves && W < 0; ++c)
+            if (paths_base_bpw(fp32, q.opts.scheme, q.N, c) > 0) W = c;
+        for (int c = want - 1; c >= 1 && W < 0; --c)
+            if (paths_base_bpw(fp32, q.opts.scheme, q.N, c) > 0) W = c;
+        if (W < 0) {
+            set_error("hs_path_features: no kernel shape for %d assets", q.N);
+            return HS_EINVAL;
+        }
+        const std::vector<unsigned char> tab = model_table(q, sc[0], fp32);
+        HS_HIP(hipMemcpyAsync(ws, tab.data(), tab.size(), hipMemcpyHostToDevice, st),
+               "upload model");
+        BasePathArgs ba{};
+        ba.model = ws;
+        ba.feat = d_out;
+        ba.P = q.P;
+        ba.n = q.n;
+        ba.N = q.N;
+        ba.W = W;
+        ba.key0 = static_cast<uint32_t>(q.opts.seed);
+        ba.key1 = static_cast<uint32_t>(q.opts.seed >> 32);
+        HS_HIP(launch_paths_base(fp32, q.opts.scheme, ft, ba, st), "base path kernel launch");
+        // the host table must outlive the asynchronous upload
+        HS_HIP(hipStreamSynchronize(st), "stream synchronize");
+        return HS_OK;
+    }
+    const Shape sh = shape_of(q);
     Pass pass;
     pass.scen = {0};
     pass.has_base_spot = true;
     PassPlan pp = plan_pass(q, sh, sc, pass, default_target_waves(), 0);
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    unsigned char* ws = static_cast<unsigned char*>(d_workspace);
     const size_t off_groups = (pp.base.size() + 255) / 256 * 256;
     HS_HIP(hipMemcpyAsync(ws, pp.base.data(), pp.base.size(), hipMemcpyHostToDevice, st),
            "upload base");

@@ -17,6 +17,14 @@ size_t paths_lds_bytes(bool fp32, int nmax);
 hipError_t launch_paths(bool fp32, int nmax, int scheme, int feat, const PathArgs& a, int nchunks,
                         int nblockgroups, hipStream_t st);
 
+// Base-scenario path kernel (features of the model alone): Philox blocks per
+// wave for N assets and W waves (1, 2 or 4; -1 if this W does not fit), its
+// dynamic LDS, and the launch over ceil(P / 64) blocks of W waves.
+int paths_base_bpw(bool fp32, int scheme, int N, int W);
+size_t paths_base_lds_bytes(bool fp32, int N, int W);
+hipError_t launch_paths_base(bool fp32, int scheme, int feat, const BasePathArgs& a,
+                             hipStream_t st);
+
 // The kernels after the path kernel are compiled per feature storage type
 // (FeatType: FP32, FP64, FP16, BF16), the path kernel per path precision,
 // scheme and storage type.

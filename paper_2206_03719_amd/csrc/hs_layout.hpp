@@ -70,6 +70,37 @@ struct GroupP {
     int32_t pad[3];
 };
 
+// Base-scenario path kernel (features of the model alone, no Greek
+// scenarios) for up to kMaxPathAssets assets.  A wave owns up to BPW = 1, 2
+// or 4 Philox blocks (asset pairs).  Waves per block: up to 16, or up to 8
+// where the kernel needs more than 128 registers (the QE scheme, and FP64
+// Euler with four blocks per wave), so that it never spills.
+constexpr int kMaxPathAssets = 64;
+constexpr int kBaseMaxWaves = 16;
+constexpr int kBaseMaxBpw = 4;
+constexpr int base_max_waves(bool fp32, bool qe, int bpw)
+{
+    return (qe || (!fp32 && bpw >= 4)) ? 8 : 16;
+}
+
+// The model in the path precision R, with the Cholesky factor of the
+// correlation in rows of kMaxPathAssets entries (upper part and rows past N
+// zero).
+template <typename R>
+struct ModelP {
+    AssetP<R> a[kMaxPathAssets];
+    R L[kMaxPathAssets * kMaxPathAssets];
+    R r, dt, invN, pad;
+};
+
+struct BasePathArgs {
+    const void* model;  // ModelP<R>
+    void* feat;         // R2 [date][path]
+    int64_t P;
+    int32_t n, N, W, pad;
+    uint32_t key0, key1;
+};
+
 struct PathArgs {
     const void* base;      // BaseP<R>
     const void* tasks;     // TaskP<R>[]

@@ -40,15 +40,15 @@ namespace hs {
 
 hs_status copy_request(const hs_model* model, const double* corr, const hs_option* option,
                        int64_t n_paths, int32_t n_steps, const hs_bumps* bumps,
-                       const hs_opts* opts, Request& q)
+                       const hs_opts* opts, Request& q, int max_assets)
 {
     if (!model || !corr || !option || !bumps || !opts) {
         set_error("null argument (model, corr, option, bumps and opts are required)");
         return HS_EINVAL;
     }
     const int N = model->n_assets;
-    if (N < 1 || N > kMaxAssets) {
-        set_error("n_assets = %d outside 1..%d", N, kMaxAssets);
+    if (N < 1 || N > max_assets) {
+        set_error("n_assets = %d outside 1..%d", N, max_assets);
         return HS_EINVAL;
     }
     const double* arr[6] = {model->S0, model->v0, model->kappa, model->theta_lr, model->xi,
@@ -111,15 +111,15 @@ int basis_m(const Request& q)
     return q.N == 1 ? 3 : 5;
 }
 
-hs_status validate(const Request& q)
+hs_status validate(const Request& q, int max_waves, uint32_t extra_flags)
 {
     const int N = q.N;
     if (q.P < 2) {
         set_error("n_paths = %lld, need >= 2", static_cast<long long>(q.P));
         return HS_EINVAL;
     }
-    if (q.P > (int64_t(1) << 40)) {
-        set_error("n_paths = %lld above 2^40", static_cast<long long>(q.P));
+    if (q.P > (int64_t(1) << 31)) {  // the path kernels run one work-item per path
+        set_error("n_paths = %lld above 2^31", static_cast<long long>(q.P));
         return HS_EINVAL;
     }
     if (q.n < 1 || q.n > 4096) {
@@ -231,11 +231,11 @@ hs_status validate(const Request& q)
         set_error("opts.precision = %d", op.precision);
         return HS_EINVAL;
     }
-    if (op.waves_per_block < 0 || op.waves_per_block > kMaxWaves) {
-        set_error("opts.waves_per_block = %d outside 0..%d", op.waves_per_block, kMaxWaves);
+    if (op.waves_per_block < 0 || op.waves_per_block > max_waves) {
+        set_error("opts.waves_per_block = %d outside 0..%d", op.waves_per_block, max_waves);
         return HS_EINVAL;
     }
-    if (op.flags & ~(HS_FLAG_EXPORT_TAU | HS_FLAG_TIMING | HS_FLAG_GRAPH)) {
+    if (op.flags & ~(HS_FLAG_EXPORT_TAU | HS_FLAG_TIMING | HS_FLAG_GRAPH | extra_flags)) {
         set_error("opts.flags = 0x%x has unknown bits", op.flags);
         return HS_EINVAL;
     }
@@ -478,6 +478,33 @@ QeP<R> qe_params(double v0, double kappa, double theta, double xi, double rho, d
     c.K3 = 0.5 * dt * (1.0 - rho * rho);
     c.K4 = 0.5 * dt * (1.0 - rho * rho);
     return c;
+}
+
+// The base model in the path precision R for the base-model path kernel.
+template <typename R>
+std::vector<unsigned char> model_table_t(const Request& q, const Scenario& b0)
+{
+    ModelP<R> mp;
+    std::memset(&mp, 0, sizeof mp);
+    const int N = q.N;
+    const double dt = q.opt.T / static_cast<double>(q.n);
+    for (int a = 0; a < N; ++a) {
+        mp.a[a].S0 = static_cast<R>(q.S0[a]);
+        mp.a[a].v0 = static_cast<R>(q.v0[a]);
+        mp.a[a].kappa = static_cast<R>(q.kappa[a]);
+        mp.a[a].theta = static_cast<R>(q.theta[a]);
+        mp.a[a].xi = static_cast<R>(q.xi[a]);
+        mp.a[a].rho = static_cast<R>(q.rho[a]);
+        mp.a[a].rhobar = static_cast<R>(std::sqrt(1.0 - q.rho[a] * q.rho[a]));
+        mp.a[a].qe = qe_params<R>(q.v0[a], q.kappa[a], q.theta[a], q.xi[a], q.rho[a], q.r, dt);
+        for (int c = 0; c <= a; ++c) mp.L[a * kMaxPathAssets + c] = static_cast<R>(b0.L[a * N + c]);
+    }
+    mp.r = static_cast<R>(q.r);
+    mp.dt = static_cast<R>(dt);
+    mp.invN = static_cast<R>(1.0 / static_cast<double>(N));
+    std::vector<unsigned char> out(sizeof mp);
+    std::memcpy(out.data(), &mp, sizeof mp);
+    return out;
 }
 
 template <typename R>
@@ -725,6 +752,11 @@ void greeks_from_prices(const Request& q, const std::vector<double>& price, hs_g
             for (int j = i + 1; j < N; ++j, ++t)
                 if (out->corr) out->corr[t] = (price[s + t] - V) / q.bumps.corr_abs;
     }
+}
+
+std::vector<unsigned char> model_table(const Request& q, const Scenario& base, bool fp32)
+{
+    return fp32 ? model_table_t<float>(q, base) : model_table_t<double>(q, base);
 }
 
 }  // namespace hs

@@ -27,10 +27,14 @@ struct Request {
     hs_opts opts{};
 };
 
+// max_assets: kMaxAssets for Greek sets, kMaxPathAssets for the base-model
+// path features.
 hs_status copy_request(const hs_model* model, const double* corr, const hs_option* option,
                        int64_t n_paths, int32_t n_steps, const hs_bumps* bumps,
-                       const hs_opts* opts, Request& out);
-hs_status validate(const Request& q);  // ranges, symmetry, SPD of every scenario
+                       const hs_opts* opts, Request& out, int max_assets = kMaxAssets);
+// Ranges and symmetry; max_waves bounds opts.waves_per_block, extra_flags
+// are the flag bits the calling entry point accepts beyond the common ones.
+hs_status validate(const Request& q, int max_waves = kMaxWaves, uint32_t extra_flags = 0u);
 
 // One scenario of the Greek set (host FP64).
 struct Scenario {
@@ -45,6 +49,9 @@ int basis_m(const Request& q);
 bool cholesky(int N, const std::vector<double>& C, std::vector<double>& L);
 hs_status expand_scenarios(const Request& q, std::vector<Scenario>& out);
 int64_t num_scenarios(int N, uint32_t mask);
+// The base scenario as the base-model path kernel's table (ModelP in the
+// path precision).
+std::vector<unsigned char> model_table(const Request& q, const Scenario& base, bool fp32);
 
 // A pass runs a subset of scenarios whose features fit the workspace at once.
 struct Pass {

@@ -160,3 +160,37 @@ def test_scheme_validation():
     assert _call(w, opts__feature_format=1, precision="fp64")[0] == hs.EINVAL
     assert _call(w, opts__feature_format=2, opts__scheme=1)[0] == hs.EINVAL
     assert _call(w, opts__feature_format=1, ws_bytes=4096)[0] == hs.ENOMEM
+
+
+def _features_call(N, flags=0, wpb=0, n_paths=1000, n_steps=16, out_bytes=1 << 34,
+                   ws_bytes=1 << 20, scheme=0):
+    w = W.best_of_call(n_assets=min(N, 64), n_paths=1000, n_steps=16)
+    m = hs._Marshal(w["model"], w["corr"], w["option"], None, 42, "fp32", flags, wpb, 0, scheme)
+    m.model.n_assets = N
+    st = hs.lib().hs_path_features(ctypes.byref(m.model), m.corr_ptr, n_paths, n_steps, 1.0,
+                                   ctypes.byref(m.opts), ctypes.c_void_p(FAKE_WS), out_bytes,
+                                   ctypes.c_void_p(FAKE_WS), ws_bytes, None)
+    return st, hs.lib().hs_last_error().decode()
+
+
+def test_path_features_validation():
+    # asset limits: 64 for the base-model kernel, 20 with the Greek-set kernel
+    assert _features_call(65)[0] == hs.EINVAL
+    assert _features_call(0)[0] == hs.EINVAL
+    st, msg = _features_call(21, flags=hs.FLAG_GREEK_SET_KERNEL)
+    assert st == hs.EINVAL and "1..20" in msg
+    # waves: 0..16 (0..8 with the Greek-set kernel); unknown flags rejected
+    assert _features_call(64, wpb=17)[0] == hs.EINVAL
+    assert _features_call(20, wpb=9, flags=hs.FLAG_GREEK_SET_KERNEL)[0] == hs.EINVAL
+    assert _features_call(20, flags=16)[0] == hs.EINVAL
+    assert _features_call(20, n_paths=(1 << 31) + 1)[0] == hs.EINVAL
+    # valid requests fail only on the sizes
+    assert _features_call(64, wpb=16, out_bytes=1000)[0] == hs.ENOMEM
+    assert _features_call(64, ws_bytes=100)[0] == hs.ENOMEM
+    assert _features_call(50, scheme=1, ws_bytes=100)[0] == hs.ENOMEM
+    assert hs.lib().hs_path_features_workspace_bytes(64) >= 64 * 64 * 8
+
+
+def test_greek_set_kernel_flag_only_for_path_features():
+    w = W.best_of_call(n_paths=1000, n_steps=16)
+    assert _call(w, flags=hs.FLAG_GREEK_SET_KERNEL)[0] == hs.EINVAL

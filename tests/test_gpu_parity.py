@@ -86,25 +86,27 @@ def test_normals(N):
 # ---------------------------------------------------------------------------
 # paths + path reduction (the paper's measured kernel)
 
+@pytest.mark.parametrize("kernel", ["base", "greek_set"])
 @pytest.mark.parametrize("N", [1, 3, 5, 12, 20])
-def test_path_features_fp64(N):
-    _say("path features fp64 N=%d" % N)
+def test_path_features_fp64(N, kernel):
+    _say("path features fp64 N=%d %s kernel" % (N, kernel))
     w = W.best_of_call(n_assets=N, n_paths=1000, n_steps=40)
     ref = oracle.features(w["model"], w["corr"], 1.0, 40, 1000, 42)
-    got = hs.path_features(w["model"], w["corr"], 1.0, 1000, 40, seed=42,
-                           precision="fp64").cpu().numpy()
+    got = hs.path_features(w["model"], w["corr"], 1.0, 1000, 40, seed=42, precision="fp64",
+                           greek_set_kernel=kernel == "greek_set").cpu().numpy()
     assert got.shape == ref.shape
     assert rel(got[..., 0], ref[..., 0]).max() <= 1e-13
     assert np.abs(got[..., 1] - ref[..., 1]).max() <= 1e-15 + 1e-13 * np.abs(ref[..., 1]).max()
 
 
+@pytest.mark.parametrize("kernel", ["base", "greek_set"])
 @pytest.mark.parametrize("N", [1, 5, 10])
-def test_path_features_fp32(N):
-    _say("path features fp32 N=%d" % N)
+def test_path_features_fp32(N, kernel):
+    _say("path features fp32 N=%d %s kernel" % (N, kernel))
     w = W.best_of_call(n_assets=N, n_paths=777, n_steps=252)
     ref = oracle.features(w["model"], w["corr"], 1.0, 252, 777, 42)
-    got = hs.path_features(w["model"], w["corr"], 1.0, 777, 252, seed=42,
-                           precision="fp32").cpu().numpy().astype(np.float64)
+    got = hs.path_features(w["model"], w["corr"], 1.0, 777, 252, seed=42, precision="fp32",
+                           greek_set_kernel=kernel == "greek_set").cpu().numpy().astype(np.float64)
     assert rel(got[..., 0], ref[..., 0]).max() <= 5e-5
     assert np.abs(got[..., 1] - ref[..., 1]).max() <= 5e-6
 

@@ -1,0 +1,205 @@
+"""GPU parity of the base-model path kernel (hs_path_features: Heston paths of
+one model and the per-date path reduction, the paper's measured stage) from 1
+to 64 assets, against the FP64 oracle on the same Philox streams.
+
+- FP64 features within 1e-13 relative (U) and 1e-13 of the largest A, for
+  asset counts past the Greek-set kernel's 20 (odd and even, up to 64), both
+  schemes, path counts with a ragged last block.
+- FP32 features: U within 5e-5 relative.  Full truncation amplifies FP32
+  rounding wherever an asset's variance touches 0 (the step's sqrt(max(v, 0)
+  dt) is steep there), and the default draws include assets far from the
+  Feller condition, whose variance touches 0 often; an FP32 path can then
+  drift off the FP64 one by up to about 1e-3 in that asset's variance for a
+  while.  So A is checked within 5e-7 on draws that satisfy the Feller
+  condition (vol of vol capped at 0.9 sqrt(2 kappa theta)), and on the
+  default draws within 1e-6 on 99% of the elements and 1e-3 at worst.
+- Bit for bit the Greek-set kernel's base features (N <= 20), and the same
+  for every waves-per-block count.
+- The paper's Table 1 problem sizes at full size, on sampled paths (the
+  oracle computes those paths one by one)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+hs = None
+
+
+def setup_module(module):
+    global hs
+    import paper_2206_03719_amd as _hs
+    hs = _hs
+    hs.lib()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def high_volvol(w):
+    m = {k: (np.array(v, copy=True) if k != "r" else v) for k, v in w["model"].items()}
+    m["xi"] = m["xi"] * 2.0
+    return dict(w, model=m)
+
+
+def check_fp64(got, ref):
+    assert got.shape == ref.shape
+    assert rel(got[..., 0], ref[..., 0]).max() <= 1e-13
+    assert np.abs(got[..., 1] - ref[..., 1]).max() <= 1e-15 + 1e-13 * np.abs(ref[..., 1]).max()
+
+
+@pytest.mark.parametrize("N,P,n,scheme", [(21, 1000, 24, "euler"), (33, 700, 20, "euler"),
+                                          (50, 1000, 16, "euler"), (64, 130, 12, "euler"),
+                                          (2, 65, 30, "euler"), (50, 300, 16, "qe"),
+                                          (63, 200, 10, "qe")])
+def test_wide_fp64(N, P, n, scheme):
+    _say("base kernel fp64 N=%d P=%d n=%d %s" % (N, P, n, scheme))
+    w = W.best_of_call(n_assets=N, n_paths=P, n_steps=n)
+    if scheme == "qe":
+        w = high_volvol(w)
+    ref = oracle.features(w["model"], w["corr"], 1.0, n, P, 42, scheme=scheme)
+    got = hs.path_features(w["model"], w["corr"], 1.0, P, n, seed=42, precision="fp64",
+                           scheme=scheme).cpu().numpy()
+    check_fp64(got, ref)
+
+
+def feller(w):
+    m = {k: (np.array(v, copy=True) if k != "r" else v) for k, v in w["model"].items()}
+    m["xi"] = np.minimum(m["xi"], 0.9 * np.sqrt(2.0 * m["kappa"] * m["theta"]))
+    return dict(w, model=m)
+
+
+@pytest.mark.parametrize("draws", ["feller", "default"])
+@pytest.mark.parametrize("N,P,n", [(30, 777, 126), (64, 300, 60), (21, 129, 252)])
+def test_wide_fp32(N, P, n, draws):
+    _say("base kernel fp32 N=%d P=%d n=%d %s draws" % (N, P, n, draws))
+    w = W.best_of_call(n_assets=N, n_paths=P, n_steps=n)
+    if draws == "feller":
+        w = feller(w)
+    ref = oracle.features(w["model"], w["corr"], 1.0, n, P, 42)
+    got = hs.path_features(w["model"], w["corr"], 1.0, P, n, seed=42,
+                           precision="fp32").cpu().numpy().astype(np.float64)
+    check_fp32(got, ref, tight=draws == "feller")
+
+
+def check_fp32(got, ref, tight, u_bar=5e-5, q=0.99, q_bar=1e-6):
+    assert rel(got[..., 0], ref[..., 0]).max() <= u_bar
+    ea = np.abs(got[..., 1] - ref[..., 1])
+    _say("  A error: quantile %.2f %.2e, max %.2e" % (q, np.quantile(ea, q), ea.max()))
+    if tight:
+        assert ea.max() <= 5e-7
+    else:
+        assert np.quantile(ea, q) <= q_bar
+        assert ea.max() <= 1e-3
+
+
+def test_wide_fp32_qe():
+    N, P, n = 40, 500, 126
+    _say("base kernel fp32 QE N=%d P=%d n=%d" % (N, P, n))
+    w = high_volvol(W.best_of_call(n_assets=N, n_paths=P, n_steps=n))
+    ref = oracle.features(w["model"], w["corr"], 1.0, n, P, 42, scheme="qe")
+    got = hs.path_features(w["model"], w["corr"], 1.0, P, n, seed=42, precision="fp32",
+                           scheme="qe").cpu().numpy().astype(np.float64)
+    # as for the Greek-set kernel: a path whose psi passes within rounding of
+    # 1.5 may take the other QE branch from there on
+    eu = rel(got[..., 0], ref[..., 0]).max(axis=0)
+    assert int((eu > 5e-5).sum()) <= 2
+    assert np.median(eu) <= 5e-6
+
+
+@pytest.mark.parametrize("precision,scheme", [("fp64", "euler"), ("fp32", "euler"),
+                                              ("fp64", "qe"), ("fp32", "qe")])
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 12, 20])
+def test_same_as_greek_set_kernel(N, precision, scheme):
+    _say("base vs Greek-set kernel N=%d %s %s" % (N, precision, scheme))
+    w = W.best_of_call(n_assets=N, n_paths=333, n_steps=30)
+    a = hs.path_features(w["model"], w["corr"], 1.0, 333, 30, seed=7, precision=precision,
+                         scheme=scheme)
+    b = hs.path_features(w["model"], w["corr"], 1.0, 333, 30, seed=7, precision=precision,
+                         scheme=scheme, greek_set_kernel=True)
+    assert bool((a == b).all())
+
+
+@pytest.mark.parametrize("N,precision,scheme", [(50, "fp32", "euler"), (21, "fp64", "euler"),
+                                                (64, "fp64", "qe"), (7, "fp32", "euler")])
+def test_waves_per_block_invariance(N, precision, scheme):
+    _say("waves per block invariance N=%d %s %s" % (N, precision, scheme))
+    w = W.best_of_call(n_assets=N, n_paths=200, n_steps=12)
+    ref = hs.path_features(w["model"], w["corr"], 1.0, 200, 12, seed=3, precision=precision,
+                           scheme=scheme)
+    for wpb in (1, 2, 3, 5, 8, 11, 16):
+        got = hs.path_features(w["model"], w["corr"], 1.0, 200, 12, seed=3, precision=precision,
+                               scheme=scheme, waves_per_block=wpb)
+        assert bool((got == ref).all()), wpb
+
+
+@pytest.mark.parametrize("features", ["fp16", "bf16"])
+def test_wide_16bit_storage_is_round_to_nearest(features):
+    import torch
+    w = W.best_of_call(n_assets=50, n_paths=500, n_steps=20)
+    f32 = hs.path_features(w["model"], w["corr"], 1.0, 500, 20, seed=42, precision="fp32")
+    f16 = hs.path_features(w["model"], w["corr"], 1.0, 500, 20, seed=42, precision="fp32",
+                           features=features)
+    want = f32.to(torch.float16 if features == "fp16" else torch.bfloat16)
+    assert torch.equal(f16.view(torch.int16), want.view(torch.int16))
+
+
+def test_smallest_requests():
+    # two paths (one ragged block of 64 lanes), one step
+    w = W.best_of_call(n_assets=64, n_paths=2, n_steps=1)
+    ref = oracle.features(w["model"], w["corr"], 1.0, 1, 2, 42)
+    got = hs.path_features(w["model"], w["corr"], 1.0, 2, 1, seed=42, precision="fp64")
+    check_fp64(got.cpu().numpy(), ref)
+    w = W.best_of_call(n_assets=1, n_paths=64, n_steps=3)
+    ref = oracle.features(w["model"], w["corr"], 1.0, 3, 64, 42)
+    got = hs.path_features(w["model"], w["corr"], 1.0, 64, 3, seed=42, precision="fp64")
+    check_fp64(got.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("draws", ["feller", "default"])
+@pytest.mark.parametrize("size", [s[0] for s in W.PAPER_SIZES])
+def test_table1_sizes_sampled(size, draws):
+    """Full Table 1 sizes, seven sampled paths (first, block edges, last).
+    Feller draws: FP64 within 1e-13, FP32 U within 2e-4 relative (the
+    rounding of the log price accumulates over up to 1260 steps) and A within
+    2e-6.  Default draws: the variance of assets far from the Feller condition
+    touches 0 often, where full truncation amplifies rounding in either
+    precision, so A is held to its median (1e-15 FP64, 1e-7 FP32) and bounded
+    at worst (1e-9 FP64, 1e-3 FP32), U to 1e-12 (FP64) and 2e-4 (FP32)."""
+    w = W.paper_size(size)
+    if draws == "feller":
+        w = feller(w)
+    N, n, P, T = w["n_assets"], w["n_steps"], w["n_paths"], w["T"]
+    _say("Table 1 %s (%s draws): N=%d n=%d P=%d" % (size, draws, N, n, P))
+    paths = [0, 1, 63, 64, 12345, P - 2, P - 1]
+    ref = oracle.features_at(w["model"], w["corr"], T, n, paths, w["seed"]).transpose(1, 0, 2)
+    bad = []
+    for precision in ("fp64", "fp32"):
+        got = hs.path_features(w["model"], w["corr"], T, P, n, seed=w["seed"],
+                               precision=precision)
+        sub = got[:, paths, :].cpu().numpy().astype(np.float64)
+        del got
+        eu = rel(sub[..., 0], ref[..., 0])
+        ea = np.abs(sub[..., 1] - ref[..., 1])
+        _say("  %s: U max rel %.2e; A median %.2e, max %.2e"
+             % (precision, eu.max(), np.median(ea), ea.max()))
+        if draws == "feller":
+            bars = (1e-13, 1.0, 1e-13 * np.abs(ref[..., 1]).max()) if precision == "fp64" \
+                else (2e-4, 1.0, 2e-6)
+        else:
+            bars = (1e-12, 1e-15, 1e-9) if precision == "fp64" else (2e-4, 1e-7, 1e-3)
+        if not (eu.max() <= bars[0] and np.median(ea) <= bars[1] and ea.max() <= bars[2]):
+            bad.append((precision, eu.max(), np.median(ea), ea.max(), bars))
+    assert not bad, bad

@@ -83,6 +83,27 @@ def best_of_call(n_assets=5, n_paths=25000, n_steps=252, seed=42, param_seed=42,
             "bumps": default_bumps(mask), "seed": seed, "precision": precision}
 
 
+# The problem-size classes of the paper's Table 1: (name, assets, daily
+# timesteps, paths).  The horizon is one trading day per step, T = steps / 252
+# years (6 months for the smallest class, 5 years for the largest).
+PAPER_SIZES = (("tiny", 5, 126, 25_000), ("small", 10, 126, 25_000),
+               ("medium", 20, 252, 25_000), ("large", 30, 504, 25_000),
+               ("huge", 50, 1260, 25_000))
+
+
+def paper_size(name, seed=42, param_seed=42, n_paths=None):
+    """One Table 1 class as a model-only workload (no option, no bumps): the
+    best-of parameter draws for that many assets, T = steps / 252."""
+    for nm, N, n, P in PAPER_SIZES:
+        if nm == name:
+            rng = np.random.default_rng(param_seed)
+            model, C = draw_assets(N, rng)
+            return {"name": "table1-%s-%dx%dx%d" % (nm, N, n, P), "model": model, "corr": C,
+                    "n_assets": N, "n_steps": n, "n_paths": P if n_paths is None else n_paths,
+                    "T": n / 252.0, "seed": seed}
+    raise KeyError(name)
+
+
 def serving_stream(n_requests, rate_per_s, seed=7, paths=(10_000, 400_000),
                    steps=(52, 126, 252, 504), assets=(1, 20), precision="fp32"):
     """Poisson arrivals of full-Greek-set requests: assets ~ U{1..20}, paths ~
