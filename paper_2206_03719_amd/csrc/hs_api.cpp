@@ -596,13 +596,18 @@ hs_status hs_path_features(const hs_model* model, const double* corr, int64_t n_
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     unsigned char* ws = static_cast<unsigned char*>(d_workspace);
     if (!greek_set) {
-        // waves: as asked (auto: one per Philox block, up to 16), then the
-        // nearest count the kernel supports for this asset count, upwards
-        // first (at most four blocks per wave; fewer waves where the variant
-        // needs more registers)
+        // waves: as asked, else (measured on the paper's problem sizes)
+        // Euler: one per Philox block up to 12 blocks, beyond that two blocks
+        // per wave; QE, whose FP64 variance step gains from several
+        // independent assets per wave: at most 4 waves.  Then the nearest
+        // count the kernel supports for this asset count, upwards first (at
+        // most four blocks per wave; fewer waves where the variant needs more
+        // registers).
         const int nblk = (q.N + 1) / 2;
-        const int want =
-            q.opts.waves_per_block > 0 ? q.opts.waves_per_block : std::min(kBaseMaxWaves, nblk);
+        const int want = q.opts.waves_per_block > 0       ? q.opts.waves_per_block
+                         : q.opts.scheme == HS_SCHEME_QE ? std::min(4, nblk)
+                         : nblk <= 12                     ? nblk
+                                                          : (nblk + 1) / 2;
         int W = -1;
         for (int c = want; c <= kBaseMaxWaves && W < 0; ++c)
             if (paths_base_bpw(fp32, q.opts.scheme, q.N, c) > 0) W = c;

@@ -442,18 +442,27 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 // kMaxPathAssets assets.
 //
 // Block = W waves x 64 lanes; lane l of every wave follows path
-// 64 * blockIdx.x + l.  Wave w owns the Philox blocks j = w + i W (i < BPW)
-// and with them the asset pairs (2j, 2j + 1): it draws their normals, keeps
-// eta in registers and publishes eps to LDS.  After the step's one barrier,
-// every wave forms Z^S = L eps for its own assets from the published eps (in
-// the order b = 0, 1, ..., as the Greek-set kernel does), advances them, and
-// leaves the largest S over its assets and each asset's max(v, 0) in LDS.
-// After the next barrier the last wave, which owns the fewest blocks, folds
-// them into the date's feature: U = max over waves, A = (1/N) x the sum of
-// max(v_i, 0) in asset order, so that the feature is the same for every W
-// and bit for bit the Greek-set kernel's base feature.  LDS is double
-// buffered by step parity: eps [2][blocks][64] pairs, max(v, 0) [2][2 blocks][64],
-// wave maxima [2][W][64].
+// 64 * blockIdx.x + l.  Wave w owns the Philox blocks own_block(w, i, W)
+// (i < BPW) and with them the asset pairs (2j, 2j + 1): it draws their
+// normals, keeps eta in registers and publishes eps to LDS.  After the step's
+// one barrier, every wave forms Z^S = L eps for its own assets from the
+// published eps (in the order b = 0, 1, ..., as the Greek-set kernel does),
+// advances them, and leaves the largest S over its assets and each asset's
+// max(v, 0) in LDS.  After the next barrier wave 0, whose rows of L are the
+// shortest, folds them into the date's feature: U = max over waves, A = (1/N)
+// x the sum of max(v_i, 0) in asset order, so that the feature is the same
+// for every W and bit for bit the Greek-set kernel's base feature.  LDS is
+// double buffered by step parity: eps [2][blocks, padded to CH][64] pairs, max(v, 0)
+// [2][2 blocks][64], wave maxima [2][W][64].
+// Philox block i of wave w among W: blocks are dealt in a snake (w, then
+// 2W - 1 - w, then 2W + w, ...), so that the triangular correlation work
+// (block j needs j + 1 rows of eps) evens out over the waves, and each
+// wave's blocks increase with i.
+__device__ __forceinline__ int own_block(int w, int i, int W)
+{
+    return (i & 1) ? (i + 1) * W - 1 - w : i * W + w;
+}
+
 template <typename R, int BPW, int SCHEME, typename FT>
 __global__ void __launch_bounds__(kLanes * base_max_waves(sizeof(R) == 4, SCHEME == HS_SCHEME_QE, BPW))
     k_paths_base(const BasePathArgs A)
@@ -463,8 +472,10 @@ __global__ void __launch_bounds__(kLanes * base_max_waves(sizeof(R) == 4, SCHEME
     const int N = A.N;
     const int W = A.W;
     const int nblk = (N + 1) / 2;
+    constexpr int CH = base_chunk(sizeof(R) == 4);
+    const int nblk_pad = (nblk + CH - 1) / CH * CH;
     R2<R>* const s_eps = reinterpret_cast<R2<R>*>(hs_smem);
-    R* const s_vp = reinterpret_cast<R*>(s_eps + 2 * nblk * kLanes);
+    R* const s_vp = reinterpret_cast<R*>(s_eps + 2 * nblk_pad * kLanes);
     R* const s_max = s_vp + 2 * (2 * nblk) * kLanes;
 
     const int lane = threadIdx.x;
@@ -487,12 +498,18 @@ __global__ void __launch_bounds__(kLanes * base_max_waves(sizeof(R) == 4, SCHEME
     VT eta[2 * BPW];
 #pragma unroll
     for (int s = 0; s < 2 * BPW; ++s) {
-        const int a = 2 * (w + (s / 2) * W) + (s & 1);
+        const int a = 2 * own_block(w, s / 2, W) + (s & 1);
         const int ac = a < N ? a : 0;  // the table is read in bounds either way
         const VT v0 = static_cast<VT>(SCHEME == HS_SCHEME_QE ? mp->a[ac].qe.v0 : mp->a[ac].v0);
         X[s] = R(0);
         V[s] = a < N ? v0 : VT(0);
         eta[s] = VT(0);
+    }
+
+    // eps pairs past the last block stay 0 (their L columns are 0 too)
+    for (int j = nblk + w; j < nblk_pad; j += W) {
+        s_eps[j * kLanes + lane] = R2<R>{R(0), R(0)};
+        s_eps[(nblk_pad + j) * kLanes + lane] = R2<R>{R(0), R(0)};
     }
 
     // the feature of the date after step kk, from the buffers of parity kk & 1
@@ -515,7 +532,7 @@ __global__ void __launch_bounds__(kLanes * base_max_waves(sizeof(R) == 4, SCHEME
     };
 
     for (int k = 0; k < A.n; ++k) {
-        R2<R>* const eb = s_eps + (k & 1) * nblk * kLanes;
+        R2<R>* const eb = s_eps + (k & 1) * nblk_pad * kLanes;
         R* const vb = s_vp + (k & 1) * (2 * nblk) * kLanes;
         R* const mb = s_max + (k & 1) * W * kLanes;
 
@@ -523,7 +540,7 @@ __global__ void __launch_bounds__(kLanes * base_max_waves(sizeof(R) == 4, SCHEME
         //    pair past an odd N is published as 0 (its L column is 0)
 #pragma unroll
         for (int i = 0; i < BPW; ++i) {
-            const int j = w + i * W;
+            const int j = own_block(w, i, W);
             if (j < nblk) {
                 const Words q = philox10(plo, static_cast<uint32_t>(k), static_cast<uint32_t>(j),
                                          phi, A.key0, A.key1);
@@ -547,30 +564,37 @@ __global__ void __launch_bounds__(kLanes * base_max_waves(sizeof(R) == 4, SCHEME
         __syncthreads();
 
         // 2) the previous date's feature
-        if (w == W - 1 && k > 0) fold(k - 1);
+        if (w == 0 && k > 0) fold(k - 1);
 
         // 3) own assets: Z^S over the published blocks 0..j of each owned
-        //    block j (the upper part of L is 0), then one step
+        //    block j, CH blocks at a time with one wait for the chunk's LDS
+        //    and scalar loads; the upper part of L is 0, so the columns a
+        //    chunk adds past a row's diagonal add 0, and slots that own no
+        //    block read the zero rows
         R z[2 * BPW];
 #pragma unroll
         for (int s = 0; s < 2 * BPW; ++s) z[s] = R(0);
         int jb = 0;
 #pragma unroll
         for (int i = 0; i < BPW; ++i) {
-            const int ji = w + i * W;
+            const int ji = own_block(w, i, W);
             const int jend = ji < nblk ? ji : -1;
-            for (; jb <= jend; ++jb) {
-                const R2<R> e = eb[jb * kLanes + lane];
+            for (; jb <= jend; jb += CH) {
+                R2<R> e[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) e[c] = eb[(jb + c) * kLanes + lane];
 #pragma unroll
                 for (int t = i; t < BPW; ++t) {
-                    const int jt = w + t * W;
-                    if (jt < nblk) {
-                        const cptr<R> l0 = mp->L + (2 * jt) * kMaxPathAssets + 2 * jb;
-                        const cptr<R> l1 = l0 + kMaxPathAssets;
-                        z[2 * t] += l0[0] * e.u;
-                        z[2 * t] += l0[1] * e.a;
-                        z[2 * t + 1] += l1[0] * e.u;
-                        z[2 * t + 1] += l1[1] * e.a;
+                    const int jt = own_block(w, t, W);
+                    const int row = 2 * (jt < nblk ? jt : kZeroPair);
+                    const cptr<R> l0 = mp->L + row * kMaxPathAssets + 2 * jb;
+                    const cptr<R> l1 = l0 + kMaxPathAssets;
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        z[2 * t] += l0[2 * c] * e[c].u;
+                        z[2 * t] += l0[2 * c + 1] * e[c].a;
+                        z[2 * t + 1] += l1[2 * c] * e[c].u;
+                        z[2 * t + 1] += l1[2 * c + 1] * e[c].a;
                     }
                 }
             }
@@ -578,7 +602,7 @@ __global__ void __launch_bounds__(kLanes * base_max_waves(sizeof(R) == 4, SCHEME
         R m = R(0);  // every S > 0
 #pragma unroll
         for (int s = 0; s < 2 * BPW; ++s) {
-            const int a = 2 * (w + (s / 2) * W) + (s & 1);
+            const int a = 2 * own_block(w, s / 2, W) + (s & 1);
             if (a < N) {
                 const cptr<AssetP<R>> q = mp->a + a;
                 if constexpr (SCHEME == HS_SCHEME_QE) {
@@ -598,7 +622,7 @@ __global__ void __launch_bounds__(kLanes * base_max_waves(sizeof(R) == 4, SCHEME
         mb[w * kLanes + lane] = m;
     }
     __syncthreads();
-    if (w == W - 1 && A.n > 0) fold(A.n - 1);
+    if (w == 0 && A.n > 0) fold(A.n - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1700,7 +1724,9 @@ size_t paths_base_lds_bytes(bool fp32, int N, int W)
 {
     const size_t R = fp32 ? 4u : 8u;
     const size_t nblk = static_cast<size_t>((N + 1) / 2);
-    return 2u * nblk * kLanes * 2u * R + 2u * (2u * nblk) * kLanes * R +
+    const size_t ch = static_cast<size_t>(base_chunk(fp32));
+    const size_t nblk_pad = (nblk + ch - 1) / ch * ch;
+    return 2u * nblk_pad * kLanes * 2u * R + 2u * (2u * nblk) * kLanes * R +
            2u * static_cast<size_t>(W) * kLanes * R;
 }
 

@@ -85,13 +85,17 @@ constexpr int base_max_waves(bool fp32, bool qe, int bpw)
 
 // The model in the path precision R, with the Cholesky factor of the
 // correlation in rows of kMaxPathAssets entries (upper part and rows past N
-// zero).
+// zero, and two more zero rows, kZeroPair, for slots that own no assets).
+constexpr int kZeroPair = kMaxPathAssets / 2;
 template <typename R>
 struct ModelP {
     AssetP<R> a[kMaxPathAssets];
-    R L[kMaxPathAssets * kMaxPathAssets];
+    R L[(kMaxPathAssets + 2) * kMaxPathAssets];
     R r, dt, invN, pad;
 };
+// Philox blocks per correlation chunk of the base-model kernel (the eps
+// buffer in LDS is padded with zeros to a whole number of chunks).
+constexpr int base_chunk(bool fp32) { return fp32 ? 4 : 2; }
 
 struct BasePathArgs {
     const void* model;  // ModelP<R>
