@@ -173,7 +173,12 @@ typedef struct hs_opts {
     int32_t scheme;          /* HS_SCHEME_EULER_FT (0) | HS_SCHEME_QE (1)          */
     int32_t feature_format;  /* HS_FEATURES_NATIVE (0) | HS_FEATURES_FP16 (1) |
                                 HS_FEATURES_BF16 (2)                               */
-    int32_t reserved[2];     /* must be zero                                       */
+    int32_t window_dates;    /* American: 0 = the backward sweep runs over all
+                                dates at once when the workspace holds them, else
+                                in windows of dates with checkpoint-recompute of
+                                the paths; > 0 (<= n_steps) = always in windows of
+                                this many dates.  Never changes results.           */
+    int32_t reserved;        /* must be zero                                       */
 } hs_opts;
 
 /* Results of a Greek set.  Caller-allocated host arrays; any may be NULL to
@@ -229,7 +234,7 @@ size_t hs_workspace_min_bytes(const hs_model *model, const hs_option *option, in
  *   out: host struct; its arrays are caller-allocated (see hs_greeks).
  * Validation happens before any device work.  Errors: HS_EINVAL (ranges,
  * NULLs, non-symmetric or non-unit-diagonal corr, theta bump T_abs >= T,
- * vega with v0_i = 0, reserved fields non-zero), HS_ENOTSPD (corr or a
+ * vega with v0_i = 0, reserved field non-zero), HS_ENOTSPD (corr or a
  * bumped corr not SPD), HS_ENOMEM (workspace too small), HS_EDEVICE. */
 hs_status hs_price_greeks(const hs_model *model, const double *corr, const hs_option *option,
                           int64_t n_paths, int32_t n_steps, const hs_bumps *bumps,

@@ -68,7 +68,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
                 ("sweep_mode", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("feature_format", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("feature_format", ctypes.c_int32), ("window_dates", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Greeks(ctypes.Structure):
@@ -168,7 +169,8 @@ class _Marshal:
     """Holds the numpy arrays the ctypes structs point into."""
 
     def __init__(self, model, corr, option, bumps=None, seed=42, precision="fp32", flags=0,
-                 waves_per_block=0, sweep_mode=0, scheme="euler", features="native"):
+                 waves_per_block=0, sweep_mode=0, scheme="euler", features="native",
+                 window_dates=0):
         self.arrs = [_f64(model[k]) for k in ("S0", "v0", "kappa", "theta", "xi", "rho")]
         N = len(self.arrs[0])
         self.N = N
@@ -187,7 +189,7 @@ class _Marshal:
         self.opts = Opts(prec, int(waves_per_block), int(seed), int(flags), int(sweep_mode),
                          SCHEMES[scheme] if isinstance(scheme, str) else int(scheme),
                          FEATURES[features] if isinstance(features, str) else int(features),
-                         (ctypes.c_int32 * 2)(0, 0))
+                         int(window_dates), 0)
 
     @property
     def corr_ptr(self):
@@ -200,9 +202,10 @@ def num_scenarios(n_assets, mask):
 
 
 def workspace_bytes(model, option, n_paths, n_steps, bumps, precision="fp32", minimum=False,
-                    flags=0, sweep_mode=0, scheme="euler", features="native"):
+                    flags=0, sweep_mode=0, scheme="euler", features="native", window_dates=0):
     m = _Marshal(model, np.eye(len(model["S0"])), option, bumps, precision=precision,
-                 flags=flags, sweep_mode=sweep_mode, scheme=scheme, features=features)
+                 flags=flags, sweep_mode=sweep_mode, scheme=scheme, features=features,
+                 window_dates=window_dates)
     f = lib().hs_workspace_min_bytes if minimum else lib().hs_workspace_bytes
     n = f(ctypes.byref(m.model), ctypes.byref(m.option), int(n_paths), int(n_steps),
           ctypes.byref(m.bumps), ctypes.byref(m.opts))
@@ -225,21 +228,24 @@ def _stream_handle(stream):
 def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="fp32",
                  workspace=None, stream=None, export_tau=False, timing=False,
                  waves_per_block=0, sweep_mode=0, graph=False, scheme="euler",
-                 features="native"):
+                 features="native", window_dates=0):
     """Price + bump-and-revalue Greeks of one option (hs_price_greeks).
 
     ``workspace``: a CUDA uint8 tensor (allocated here when None).  ``graph``:
-    replay the pass's kernels from a cached HIP graph.  Returns a dict of numpy
+    replay the pass's kernels from a cached HIP graph.  ``window_dates``: run
+    the backward sweep in windows of that many dates with checkpoint-recompute
+    of the paths (0: only if the workspace needs it).  Returns a dict of numpy
     arrays / floats."""
     torch = _torch()
     flags = ((FLAG_EXPORT_TAU if export_tau else 0) | (FLAG_TIMING if timing else 0) |
              (FLAG_GRAPH if graph else 0))
     m = _Marshal(model, corr, option, bumps, seed, precision, flags, waves_per_block, sweep_mode,
-                 scheme, features)
+                 scheme, features, window_dates)
     N = m.N
     if workspace is None:
         nbytes = workspace_bytes(model, option, n_paths, n_steps, bumps, precision, flags=flags,
-                                 sweep_mode=sweep_mode, scheme=scheme, features=features)
+                                 sweep_mode=sweep_mode, scheme=scheme, features=features,
+                                 window_dates=window_dates)
         workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     S = num_scenarios(N, m.bumps.mask)
     out_arrays = {"delta": np.zeros(N), "gamma": np.zeros(N), "vega": np.zeros(N),
@@ -353,7 +359,8 @@ class Server:
     def submit(self, w, precision=None):
         m = _Marshal(w["model"], w["corr"], w["option"], w["bumps"], w.get("seed", 42),
                      precision or w.get("precision", "fp32"), scheme=w.get("scheme", "euler"),
-                     features=w.get("features", "native"))
+                     features=w.get("features", "native"),
+                     window_dates=w.get("window_dates", 0))
         req = Request(m.model, m.corr_ptr, m.option, int(w["n_paths"]), int(w["n_steps"]),
                       m.bumps, m.opts)
         t = ctypes.c_uint64()

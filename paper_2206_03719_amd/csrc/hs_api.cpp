@@ -106,6 +106,7 @@ struct PassLaunch {
     int scheme = HS_SCHEME_EULER_FT;
     int feat = kFeatF32;
     int nmax = 0, nchunks = 0, nbg = 0, Sp = 0, cluster_q = 0, per_launch = 0, sweep_q = 0;
+    int window = 0;  // dates per window of a checkpoint-recompute pass, else 0
     int64_t part_count = 0;
     PathArgs pa{};
     LsmcArgs la{};
@@ -113,31 +114,85 @@ struct PassLaunch {
     int32_t* err_flag = nullptr;
 };
 
+hipError_t enqueue_sweep(const PassLaunch& L, const LsmcArgs& la, hipStream_t st)
+{
+    hipError_t e;
+    if (L.cluster) {
+        ClusterArgs ca = L.ca;
+        for (int s0 = 0; s0 < L.Sp; s0 += L.per_launch) {
+            ca.s0 = s0;
+            if ((e = launch_sweep_cluster(L.feat, L.cluster_q, L.keep, la, ca,
+                                          std::min(L.per_launch, L.Sp - s0), st)) != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    }
+    return launch_sweep(L.feat, L.sweep_q, la, L.Sp, st);
+}
+
+// Events ev[0..3] (optional) bracket the path kernel, the Gram kernel and the
+// sweep; in a windowed pass ev[1] follows the first path launch and the
+// windows (recompute, Gram, sweep) count as the sweep.
 hipError_t enqueue_pass(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
 {
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.err_flag), 1, 0, st)) != hipSuccess)
         return e;
-    if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.feat, L.pa, L.nchunks, L.nbg, st)) !=
+    auto fill_slots = [&]() {
+        return L.cluster ? launch_fill_u64(reinterpret_cast<uint64_t*>(L.ca.partials),
+                                           L.part_count, kEmptySlot, st)
+                         : hipSuccess;
+    };
+    if (L.window == 0) {
+        if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.feat, L.pa, L.nchunks, L.nbg, st)) !=
+            hipSuccess)
+            return e;
+        if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+        if (L.american && (e = launch_gram(L.feat, L.la, L.Sp, st)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+        if ((e = fill_slots()) != hipSuccess) return e;
+        if ((e = enqueue_sweep(L, L.la, st)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
+        return hipSuccess;
+    }
+    // checkpoint-recompute: every step once, keeping the checkpoints and the
+    // last window's features; then window by window from the last date back,
+    // recomputing each earlier window's features from its checkpoint
+    const int n = L.la.n, c = L.window;
+    PathArgs pa = L.pa;
+    pa.k_begin = 0;
+    pa.k_end = n;
+    pa.k_feat0 = n - c;
+    pa.ck_store = 1;
+    if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.feat, pa, L.nchunks, L.nbg, st)) !=
         hipSuccess)
         return e;
     if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-    if (L.american && (e = launch_gram(L.feat, L.la, L.Sp, st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-    if (L.cluster) {
-        if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.ca.partials), L.part_count,
-                                 kEmptySlot, st)) != hipSuccess)
-            return e;
-        ClusterArgs ca = L.ca;
-        for (int s0 = 0; s0 < L.Sp; s0 += L.per_launch) {
-            ca.s0 = s0;
-            if ((e = launch_sweep_cluster(L.feat, L.cluster_q, L.keep, L.la, ca,
-                                          std::min(L.per_launch, L.Sp - s0), st)) != hipSuccess)
+    if ((e = fill_slots()) != hipSuccess) return e;
+    for (int w = 0;; ++w) {
+        const int hi = n - w * c;
+        const int lo = std::max(1, hi - c + 1);
+        if (w > 0) {
+            PathArgs pr = L.pa;
+            pr.k_begin = lo - 1;
+            pr.k_end = hi;
+            pr.k_feat0 = lo - 1;
+            pr.ck_store = 0;
+            if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.feat, pr, L.nchunks, L.nbg, st)) !=
+                hipSuccess)
                 return e;
         }
-    } else {
-        if ((e = launch_sweep(L.feat, L.sweep_q, L.la, L.Sp, st)) != hipSuccess) return e;
+        LsmcArgs la = L.la;
+        la.k_lo = lo;
+        la.k_hi = hi;
+        la.f_date0 = lo;
+        la.win_first = w == 0 ? 1 : 0;
+        la.win_last = lo == 1 ? 1 : 0;
+        if ((e = launch_gram(L.feat, la, L.Sp, st)) != hipSuccess) return e;
+        if ((e = enqueue_sweep(L, la, st)) != hipSuccess) return e;
+        if (lo == 1) break;
     }
     if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
     return hipSuccess;
@@ -165,6 +220,7 @@ hipError_t launch_pass_graph(const PassLaunch& L, void* ws, hipStream_t st)
     append_bytes(key, L.per_launch);
     append_bytes(key, L.sweep_q);
     append_bytes(key, L.part_count);
+    append_bytes(key, L.window);
     append_bytes(key, L.pa);
     append_bytes(key, L.la);
     append_bytes(key, L.ca);
@@ -309,6 +365,16 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         pa.store_all = sh.american ? 1 : 0;
         pa.key0 = static_cast<uint32_t>(q.opts.seed);
         pa.key1 = static_cast<uint32_t>(q.opts.seed >> 32);
+        pa.k_begin = 0;
+        pa.k_end = q.n;
+        pa.k_feat0 = 0;
+        L.window = sh.american ? pass.window : 0;
+        if (L.window > 0) pa.plane = static_cast<int64_t>(L.window) * q.P;
+        pa.ck_every = L.window;
+        pa.ck_store = 0;
+        pa.ck_slots = q.N + pp.ntasks;
+        pa.ckx = ws + pp.lay.ckx;
+        pa.ckv = ws + pp.lay.ckv;
 
         LsmcArgs& la = L.la;
         la.feat = pa.feat;
@@ -328,6 +394,11 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         la.inv_K = 1.0 / q.opt.K;
         la.inv_tbar = 1.0 / tbar;
         la.export_tau = (q.opts.flags & HS_FLAG_EXPORT_TAU) ? 1 : 0;
+        la.k_lo = 1;
+        la.k_hi = q.n;
+        la.f_date0 = sh.american ? 1 : q.n;
+        la.win_first = 1;
+        la.win_last = 1;
 
         // backward sweep: a cluster of workgroups per scenario when it fits the
         // device, else one workgroup per scenario with the state in the workspace
@@ -349,7 +420,8 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
                 L.cluster = false;
             }
         }
-        L.sweep_q = sh.sweep == kSweepBlockRegs ? sh.sweep_q : 0;
+        // windows keep the sweep's state in the workspace between launches
+        L.sweep_q = sh.sweep == kSweepBlockRegs && L.window == 0 ? sh.sweep_q : 0;
         if (L.cluster) {
             L.cluster_q = sh.cluster_q;
             L.per_launch = std::max(1, cap / sh.cluster_g);
@@ -433,11 +505,19 @@ size_t workspace_bound(const Request& q, bool minimum)
     const Shape sh = shape_of(q);
     const int N = q.N;
     const int64_t S = num_scenarios(N, q.bumps.mask);
-    if (!minimum) return layout_for(q, sh, static_cast<int>(S), static_cast<int>(S * N),
-                                    static_cast<int>(S) + 2 * kMaxWaves).total;
-    const int head = 1 + ((q.bumps.mask & HS_BUMP_DELTA_GAMMA) ? 2 * N : 0);
-    return std::max(layout_for(q, sh, head, N, 1 + 2 * kMaxWaves).total,
-                    layout_for(q, sh, 1, N, 1 + 2 * kMaxWaves).total);
+    // one pass over every scenario at once, unless windows are forced
+    if (!minimum && q.opts.window_dates == 0)
+        return layout_for(q, sh, static_cast<int>(S), static_cast<int>(S * N),
+                          static_cast<int>(S) + 2 * kMaxWaves)
+            .total;
+    // the planner's minimum: the largest unit, in windows of dates where that
+    // is smaller (with forced windows every unit runs in them, so this is also
+    // the size of one pass); the size does not depend on the correlation values
+    std::vector<Scenario> sc;
+    if (expand_scenarios(q, sc) != HS_OK) return 0;
+    size_t mn = 0;
+    (void)make_passes(q, sh, sc, 0, &mn);
+    return mn;
 }
 
 }  // namespace hs
@@ -657,6 +737,10 @@ hs_status hs_path_features(const hs_model* model, const double* corr, int64_t n_
     pa.store_all = 1;
     pa.key0 = static_cast<uint32_t>(q.opts.seed);
     pa.key1 = static_cast<uint32_t>(q.opts.seed >> 32);
+    pa.k_begin = 0;
+    pa.k_end = q.n;
+    pa.k_feat0 = 0;
+    pa.ck_every = 0;  // all dates, no checkpoints
     HS_HIP(launch_paths(sh.fp32, sh.nmax, q.opts.scheme, sh.feat, pa, pp.nchunks, pp.nbg, st),
            "path kernel launch");
     // the host tables must outlive the asynchronous uploads

@@ -217,7 +217,7 @@ __device__ __forceinline__ void qe_step(CP c, R zx, double zv, R& X, double& v)
 // normals (eps, eta), the base scenario's correlated normals Z^S, exp(X) and
 // max(v, 0), each [asset][lane]; under QE the variance normal eta and the
 // variance state are FP64 (VT) in both path precisions.
-template <typename R, int NMAX, int TMAX, int SCHEME, typename FT>
+template <typename R, int NMAX, int TMAX, int SCHEME, typename FT, bool CK>
 __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 {
     using VT = std::conditional_t<SCHEME == HS_SCHEME_QE, double, R>;
@@ -269,7 +269,37 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                             : VT(0);
     }
 
-    for (int k = 0; k < A.n; ++k) {
+    // checkpoint-recompute: the state at date n - (i + 2) c, checkpoint i,
+    // lives at [(i slots + slot) P + p]; the base assets are kept by block
+    // group 0 and read by every group, a task by the wave that owns it
+    R* const ckx = static_cast<R*>(A.ckx);
+    VT* const ckv = static_cast<VT*>(A.ckv);
+    // (one lane pointer per array and wave-uniform slot offsets; compiled in
+    // only for windowed passes, CK)
+    if (CK && A.k_begin > 0 && live) {
+        const int64_t row0 =
+            static_cast<int64_t>((A.n - A.k_begin) / A.ck_every - 2) * A.ck_slots;
+        const R* const bx = ckx + row0 * P + p;
+        const VT* const bv = ckv + row0 * P + p;
+#pragma unroll
+        for (int i = 0; i < kOwnPerWave; ++i) {
+            const int a = w + i * W;
+            if (a < N) {
+                Xo[i] = bx[static_cast<int64_t>(a) * P];
+                Vo[i] = bv[static_cast<int64_t>(a) * P];
+            }
+        }
+        const int64_t t0 = static_cast<int64_t>(N + g_task0) * P;
+#pragma unroll
+        for (int t = 0; t < TMAX; ++t) {
+            if (t < ntask) {
+                tX[t] = bx[t0 + static_cast<int64_t>(t) * P];
+                tV[t] = bv[t0 + static_cast<int64_t>(t) * P];
+            }
+        }
+    }
+
+    for (int k = A.k_begin; k < A.k_end; ++k) {
         R* const buf = lds + (k & 1) * 5 * SLAB;
         R* const s_eps = buf;
         VT* const s_eta = SCHEME == HS_SCHEME_QE ? lds_eta + (k & 1) * SLAB
@@ -326,8 +356,8 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
         __syncthreads();
 
         // 3) features
-        const bool store = A.store_all || k == A.n - 1;
-        const int64_t off = (A.store_all ? static_cast<int64_t>(k) * P : 0) + p;
+        const bool store = A.store_all ? k >= A.k_feat0 : k == A.n - 1;
+        const int64_t off = (A.store_all ? static_cast<int64_t>(k - A.k_feat0) * P : 0) + p;
         R eps[NMAX], E[NMAX], Sb[NMAX], vpb[NMAX], pm[NMAX], sm[NMAX], ps[NMAX];
 #pragma unroll
         for (int a = 0; a < NMAX; ++a) {
@@ -430,6 +460,34 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
                         f.a = static_cast<FT>(runS * invN);
                         feat[T->scen * A.plane + off] = f;
                     }
+                }
+            }
+        }
+
+        // 5) the state at a checkpoint date (where a window other than the
+        //    last two dates' windows starts over)
+        const int d = k + 1;
+        if (CK && A.ck_store && (A.n - d) % A.ck_every == 0 && (A.n - d) / A.ck_every >= 2 &&
+            live) {
+            const int64_t row0 = static_cast<int64_t>((A.n - d) / A.ck_every - 2) * A.ck_slots;
+            R* const bx = ckx + row0 * P + p;
+            VT* const bv = ckv + row0 * P + p;
+            if (blockIdx.y == 0) {
+#pragma unroll
+                for (int i = 0; i < kOwnPerWave; ++i) {
+                    const int a = w + i * W;
+                    if (a < N) {
+                        bx[static_cast<int64_t>(a) * P] = Xo[i];
+                        bv[static_cast<int64_t>(a) * P] = Vo[i];
+                    }
+                }
+            }
+            const int64_t t0 = static_cast<int64_t>(N + g_task0) * P;
+#pragma unroll
+            for (int t = 0; t < TMAX; ++t) {
+                if (t < ntask) {
+                    bx[t0 + static_cast<int64_t>(t) * P] = tX[t];
+                    bv[t0 + static_cast<int64_t>(t) * P] = tV[t];
                 }
             }
         }
@@ -797,9 +855,9 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const LsmcArgs A)
     constexpr int U1 = 8;  // loads in flight per thread
     __shared__ double red[(kGramThreads / 64 + 1) * 12];
     const int s = blockIdx.y;
-    const int k = blockIdx.x + 1;
-    const R2<R>* __restrict__ F =
-        static_cast<const R2<R>*>(A.feat) + s * A.plane + static_cast<int64_t>(k - 1) * A.P;
+    const int k = blockIdx.x + A.k_lo;
+    const R2<R>* __restrict__ F = static_cast<const R2<R>*>(A.feat) + s * A.plane +
+                                  static_cast<int64_t>(k - A.f_date0) * A.P;
     const int nw = kGramThreads / 64;
     const int64_t P = A.P;
     const bool two = A.m == 5;  // the basis has w terms
@@ -932,8 +990,9 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
 
     double* const gcf = GLB ? A.cf + static_cast<int64_t>(s) * P : nullptr;
     int32_t* const gtau = GLB ? A.tau + static_cast<int64_t>(s) * P : nullptr;
-    const int64_t last = A.american ? static_cast<int64_t>(n - 1) * P : 0;
+    const int64_t last = static_cast<int64_t>(n - A.f_date0) * P;  // date n
 
+    // (windows of dates keep the state in the workspace, GLB)
     double cf[GLB ? 1 : Q];
     int tau[GLB ? 1 : Q];
     if (!GLB) {
@@ -943,7 +1002,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
             cf[i] = p < P ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) : 0.0;
             tau[i] = n;
         }
-    } else {
+    } else if (A.win_first) {
         for (int64_t p = threadIdx.x; p < P; p += kSweepThreads) {
             gcf[p] = payoff(A.cp, A.K, static_cast<double>(F[last + p].u));
             gtau[p] = n;
@@ -953,14 +1012,14 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
     double skipped = 0.0;
     const int m = A.m;
     if (A.american) {
-        for (int k = n - 1; k >= 1; --k) {
+        for (int k = min(A.k_hi, n - 1); k >= A.k_lo; --k) {
             const RegRec* rr = A.reg + static_cast<int64_t>(s) * n + (k - 1);
             if (rr->ok == 0.0) {
                 skipped += 1.0;
                 continue;
             }
             const double cU = rr->cU, cA = rr->cA;
-            const R2<R>* __restrict__ Fk = F + static_cast<int64_t>(k - 1) * P;
+            const R2<R>* __restrict__ Fk = F + static_cast<int64_t>(k - A.f_date0) * P;
             double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             if (!GLB) {
 #pragma unroll
@@ -1043,6 +1102,12 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
         }
     }
 
+    double* const o = A.out + static_cast<int64_t>(s) * 4;
+    if (!A.win_last) {  // a window before the last: the state stays in the workspace
+        if (threadIdx.x == 0) o[2] = (A.win_first ? 0.0 : o[2]) + skipped;
+        return;
+    }
+
     // price: mean of CF exp(-r tau dt), then the sample standard deviation
     double s1[1] = {0.0};
     if (!GLB) {
@@ -1075,10 +1140,9 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
     }
     block_sum<1>(s2, red, NW);
     if (threadIdx.x == 0) {
-        double* o = A.out + static_cast<int64_t>(s) * 4;
         o[0] = mean;
         o[1] = sqrt(s2[0] / static_cast<double>(P - 1) / static_cast<double>(P));
-        o[2] = skipped;
+        o[2] = (A.win_first ? 0.0 : o[2]) + skipped;
         o[3] = 0.0;
     }
 }
@@ -1208,7 +1272,11 @@ __global__ void __launch_bounds__(kClusterThreads,
     const cptr<double> dsc = as_const<double>(A.disc) + static_cast<int64_t>(s) * (n + 1);
     const cptr<double> idsc = as_const<double>(A.idisc) + static_cast<int64_t>(s) * (n + 1);
     const int64_t pbase = static_cast<int64_t>(g) * (kClusterThreads * Q) + threadIdx.x;
-    const int64_t last = A.american ? static_cast<int64_t>(n - 1) * P : 0;
+    const int f0 = A.f_date0;
+    const int64_t last = static_cast<int64_t>(n - f0) * P;  // date n
+    const int k_lo = A.k_lo;
+    const int k_top = min(A.k_hi, n - 1);  // first regression date of this launch
+    double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase;
     int par = 0;
 
     // State per path: the cash flow discounted to time 0, D = h_tau exp(-r tau
@@ -1222,8 +1290,10 @@ __global__ void __launch_bounds__(kClusterThreads,
     const int64_t room = P - pbase;
     const int nlive = room <= 0 ? 0 : (room + kClusterThreads - 1) / kClusterThreads;
     int32_t* const tau = A.export_tau ? A.tau + static_cast<int64_t>(s) * P + pbase : nullptr;
+    // (a window after the first takes D from the workspace, where the
+    // previous window left it)
     double D[Q];
-    {
+    if (A.win_first) {
         const double dn = dsc[n];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -1231,6 +1301,9 @@ __global__ void __launch_bounds__(kClusterThreads,
             D[i] = i < nlive ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) * dn : 0.0;
             if (tau && i < nlive) tau[i * kClusterThreads] = n;
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) D[i] = i < nlive ? dstate[i * kClusterThreads] : 0.0;
     }
 
     double beta[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1258,26 +1331,26 @@ __global__ void __launch_bounds__(kClusterThreads,
             hh[i] = 0.0;
             xx[i] = 0.0;
             ww[i] = 0.0;
-            if (i < nlive && n >= 2) {
-                const R2<R> f = F[static_cast<int64_t>(n - 2) * P + p];
+            if (i < nlive && k_top >= k_lo) {
+                const R2<R> f = F[static_cast<int64_t>(k_top - f0) * P + p];
                 cu[i] = f.u;
                 ca[i] = f.a;
             }
-            if (i < nlive && n >= 3) {
-                const R2<R> f = F[static_cast<int64_t>(n - 3) * P + p];
+            if (i < nlive && k_top - 1 >= k_lo) {
+                const R2<R> f = F[static_cast<int64_t>(k_top - 1 - f0) * P + p];
                 nu[i] = f.u;
                 na[i] = f.a;
             }
         }
         // regression-set flag and means of date k, loaded one date ahead
-        double r_ok = n >= 2 ? recs[n - 2].ok : 0.0;
-        double r_cU = n >= 2 ? recs[n - 2].cU : 0.0;
-        double r_cA = n >= 2 ? recs[n - 2].cA : 0.0;
+        double r_ok = k_top >= k_lo ? recs[k_top - 1].ok : 0.0;
+        double r_cU = k_top >= k_lo ? recs[k_top - 1].cU : 0.0;
+        double r_cA = k_top >= k_lo ? recs[k_top - 1].cA : 0.0;
         double bcU = 0.0, bcA = 0.0;  // regression-set means of date k+1
-        for (int k = n - 1; k >= 1; --k) {
+        for (int k = k_top; k >= k_lo; --k) {
             const bool ok = r_ok != 0.0;
             const double cU = r_cU, cA = r_cA;
-            if (k > 1) {
+            if (k > k_lo) {
                 r_ok = recs[k - 2].ok;
                 r_cU = recs[k - 2].cU;
                 r_cA = recs[k - 2].cA;
@@ -1351,8 +1424,8 @@ __global__ void __launch_bounds__(kClusterThreads,
             // date k-2 for two iterations on, issued after the exchange, whose
             // slot polls would otherwise wait for these loads (vector loads
             // complete in order)
-            if (k > 2) {
-                const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 3) * P;
+            if (k - 2 >= k_lo) {
+                const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 2 - f0) * P;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     if (i < nlive) {
@@ -1375,8 +1448,8 @@ __global__ void __launch_bounds__(kClusterThreads,
                 na[i] = ta;
             }
         }
-        if (have) {  // exercise at date 1
-            const double d1 = dsc[1];
+        if (have) {  // exercise at date k_lo (1 in the last window)
+            const double d1 = dsc[k_lo];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 double h, x, w;
@@ -1397,11 +1470,22 @@ __global__ void __launch_bounds__(kClusterThreads,
                                         beta[4] * (x * w);
                     if (h > cont) {
                         D[i] = h * d1;
-                        if (tau) tau[i * kClusterThreads] = 1;
+                        if (tau) tau[i * kClusterThreads] = k_lo;
                     }
                 }
             }
         }
+    }
+
+    if (!A.win_last) {  // a window before the last: D waits in the workspace
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            if (i < nlive) dstate[i * kClusterThreads] = D[i];
+        if (g == 0 && threadIdx.x == 0) {
+            double* o = A.out + static_cast<int64_t>(s) * 4;
+            o[2] = (A.win_first ? 0.0 : o[2]) + skipped;
+        }
+        return;
     }
 
     // price and standard error over the whole scenario
@@ -1428,7 +1512,7 @@ __global__ void __launch_bounds__(kClusterThreads,
         double* o = A.out + static_cast<int64_t>(s) * 4;
         o[0] = mean;
         o[1] = sqrt(s2[0] / static_cast<double>(P - 1) / static_cast<double>(P));
-        o[2] = skipped;
+        o[2] = (A.win_first ? 0.0 : o[2]) + skipped;
         o[3] = 0.0;
     }
 }
@@ -1486,38 +1570,45 @@ __global__ void k_normals(uint32_t k0, uint32_t k1, int N, int64_t P, int n, R* 
     }
 }
 
-template <typename R, int NMAX, int TMAX, int SCHEME, typename FT>
-hipError_t launch_paths_t(const PathArgs& a, int nchunks, int nbg, hipStream_t st)
+template <typename R, int NMAX, int TMAX, int SCHEME, typename FT, bool CK>
+hipError_t launch_paths_ck(const PathArgs& a, int nchunks, int nbg, hipStream_t st)
 {
     const size_t lds = 2u * 5u * NMAX * kLanes * sizeof(R) +
                        (SCHEME == HS_SCHEME_QE ? 2u * NMAX * kLanes * sizeof(double) : 0u);
     if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_paths<R, NMAX, TMAX, SCHEME, FT>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_paths<R, NMAX, TMAX, SCHEME, FT, CK>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                                  static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
     dim3 grid(nchunks, nbg), block(kLanes, a.W);
-    hipLaunchKernelGGL((k_paths<R, NMAX, TMAX, SCHEME, FT>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((k_paths<R, NMAX, TMAX, SCHEME, FT, CK>), grid, block, lds, st, a);
     return hipGetLastError();
+}
+
+template <typename R, int NMAX, int TMAX, int SCHEME, typename FT>
+hipError_t launch_paths_t(const PathArgs& a, int nchunks, int nbg, hipStream_t st)
+{
+    return a.ck_every > 0 ? launch_paths_ck<R, NMAX, TMAX, SCHEME, FT, true>(a, nchunks, nbg, st)
+                          : launch_paths_ck<R, NMAX, TMAX, SCHEME, FT, false>(a, nchunks, nbg, st);
 }
 
 template <typename R, int SCHEME, typename FT>
 hipError_t launch_paths_r(int nmax, const PathArgs& a, int nchunks, int nbg, hipStream_t st)
 {
-    constexpr bool F = sizeof(R) == 4;
+    constexpr bool F = sizeof(R) == 4, Q = SCHEME == HS_SCHEME_QE;
     switch (nmax) {
-    case 1: return launch_paths_t<R, 1, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 2: return launch_paths_t<R, 2, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 3: return launch_paths_t<R, 3, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 4: return launch_paths_t<R, 4, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 5: return launch_paths_t<R, 5, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 6: return launch_paths_t<R, 6, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 8: return launch_paths_t<R, 8, F ? 32 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 10: return launch_paths_t<R, 10, F ? 24 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 12: return launch_paths_t<R, 12, F ? 24 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 16: return launch_paths_t<R, 16, F ? 20 : 16, SCHEME, FT>(a, nchunks, nbg, st);
-    case 20: return launch_paths_t<R, 20, 20, SCHEME, FT>(a, nchunks, nbg, st);
+    case 1: return launch_paths_t<R, 1, paths_tmax_for(F, Q, 1), SCHEME, FT>(a, nchunks, nbg, st);
+    case 2: return launch_paths_t<R, 2, paths_tmax_for(F, Q, 2), SCHEME, FT>(a, nchunks, nbg, st);
+    case 3: return launch_paths_t<R, 3, paths_tmax_for(F, Q, 3), SCHEME, FT>(a, nchunks, nbg, st);
+    case 4: return launch_paths_t<R, 4, paths_tmax_for(F, Q, 4), SCHEME, FT>(a, nchunks, nbg, st);
+    case 5: return launch_paths_t<R, 5, paths_tmax_for(F, Q, 5), SCHEME, FT>(a, nchunks, nbg, st);
+    case 6: return launch_paths_t<R, 6, paths_tmax_for(F, Q, 6), SCHEME, FT>(a, nchunks, nbg, st);
+    case 8: return launch_paths_t<R, 8, paths_tmax_for(F, Q, 8), SCHEME, FT>(a, nchunks, nbg, st);
+    case 10: return launch_paths_t<R, 10, paths_tmax_for(F, Q, 10), SCHEME, FT>(a, nchunks, nbg, st);
+    case 12: return launch_paths_t<R, 12, paths_tmax_for(F, Q, 12), SCHEME, FT>(a, nchunks, nbg, st);
+    case 16: return launch_paths_t<R, 16, paths_tmax_for(F, Q, 16), SCHEME, FT>(a, nchunks, nbg, st);
+    case 20: return launch_paths_t<R, 20, paths_tmax_for(F, Q, 20), SCHEME, FT>(a, nchunks, nbg, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1641,10 +1732,9 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream
     return hipGetLastError();
 }
 
-int paths_tmax(bool fp32, int nmax)
+int paths_tmax(bool fp32, int scheme, int nmax)
 {
-    if (fp32) return nmax <= 8 ? 32 : nmax <= 12 ? 24 : 20;
-    return nmax <= 16 ? 16 : 20;
+    return paths_tmax_for(fp32, scheme == HS_SCHEME_QE, nmax);
 }
 
 int paths_nmax_bucket(int N)
@@ -1663,6 +1753,15 @@ size_t paths_lds_bytes(bool fp32, int nmax)
 hipError_t launch_paths(bool fp32, int nmax, int scheme, int ft, const PathArgs& a, int nchunks,
                         int nbg, hipStream_t st)
 {
+    // the step range, and a restart only from a kept checkpoint
+    if (a.k_begin < 0 || a.k_end > a.n || a.k_begin > a.k_end || a.k_feat0 < 0 ||
+        a.ck_every < 0)
+        return hipErrorInvalidValue;
+    if (a.ck_every == 0 && (a.k_begin != 0 || a.ck_store))
+        return hipErrorInvalidValue;
+    if (a.ck_every > 0 && a.k_begin > 0 &&
+        ((a.n - a.k_begin) % a.ck_every != 0 || (a.n - a.k_begin) / a.ck_every < 2))
+        return hipErrorInvalidValue;
     if (!fp32) {
         if (ft != kFeatF64) return hipErrorInvalidValue;
         return scheme == HS_SCHEME_QE
@@ -1754,13 +1853,16 @@ hipError_t launch_paths_base(bool fp32, int scheme, int ft, const BasePathArgs& 
 template <typename R>
 hipError_t launch_gram_r(const LsmcArgs& a, int S, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_gram<R>), dim3(a.n - 1, S), dim3(kGramThreads), 0, st, a);
+    const int top = std::min(a.k_hi, a.n - 1);
+    hipLaunchKernelGGL((k_gram<R>), dim3(top - a.k_lo + 1, S), dim3(kGramThreads), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_gram(int ft, const LsmcArgs& a, int S, hipStream_t st)
 {
-    if (a.n < 2) return hipSuccess;
+    if (std::min(a.k_hi, a.n - 1) < a.k_lo) return hipSuccess;
+    if (a.k_lo < 1 || a.k_hi > a.n || a.f_date0 < 1 || a.f_date0 > a.k_lo)
+        return hipErrorInvalidValue;
     return with_feat(ft, hipErrorInvalidValue, [&](auto tag) {
         return launch_gram_r<std::remove_pointer_t<decltype(tag)>>(a, S, st);
     });

@@ -12,7 +12,7 @@ namespace hs {
 // Path kernel: the asset-count bucket (1,2,3,4,5,6,8,10,12,16,20) that holds N,
 // tasks per wave for a bucket, and the dynamic LDS it needs.
 int paths_nmax_bucket(int N);
-int paths_tmax(bool fp32, int nmax);
+int paths_tmax(bool fp32, int scheme, int nmax);
 size_t paths_lds_bytes(bool fp32, int nmax);
 hipError_t launch_paths(bool fp32, int nmax, int scheme, int feat, const PathArgs& a, int nchunks,
                         int nblockgroups, hipStream_t st);

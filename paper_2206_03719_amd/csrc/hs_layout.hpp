@@ -16,6 +16,17 @@ constexpr int kGramThreads = 256; // Gram kernel block
 constexpr int kSweepThreads = 1024;
 constexpr int kRegRec = 20;       // doubles per (scenario, date) regression record
 
+// Tasks per wave of the Greek-set path kernel for its asset-count bucket
+// nmax (at least nmax: the maturity and rate scenarios have a task per
+// asset).  The QE scheme's FP64 variance state and FP64 paths take fewer, so
+// that the kernel's registers hold them.
+constexpr int paths_tmax_for(bool fp32, bool qe, int nmax)
+{
+    return !fp32 ? (nmax > 8 ? nmax : 8)
+           : qe  ? (nmax > 16 ? nmax : 16)
+                 : (nmax <= 8 ? 32 : nmax <= 12 ? 24 : 20);
+}
+
 // Storage type of the path features (U, A) in the workspace.
 enum FeatType { kFeatF32 = 0, kFeatF64 = 1, kFeatF16 = 2, kFeatBF16 = 3 };
 constexpr size_t feat_bytes(int ft) { return ft == kFeatF64 ? 16 : ft == kFeatF32 ? 8 : 4; }
@@ -105,6 +116,16 @@ struct BasePathArgs {
     uint32_t key0, key1;
 };
 
+// Checkpoint-recompute: a Greek set whose features do not fit its workspace
+// runs the backward sweep in windows of ck_every dates, from the last window
+// to the first.  The path kernel's first launch runs every step and keeps the
+// path state (every base asset and every task, per path) at the dates n - c,
+// n - 2c, ... > 0; each later window restarts from its checkpoint and
+// recomputes only its own dates' features.  Window w holds dates
+// max(1, n - (w + 1) c + 1) .. n - w c; the first launch writes window 0's
+// features, and window w >= 1 starts from the state at date n - (w + 1) c,
+// checkpoint i = w - 1: ckx [i][slot][P] (log price, R) and ckv [i][slot][P]
+// (variance, R or FP64 under QE), slot = asset (base) or N + task index.
 struct PathArgs {
     const void* base;      // BaseP<R>
     const void* tasks;     // TaskP<R>[]
@@ -114,6 +135,13 @@ struct PathArgs {
     int64_t plane;         // elements per scenario plane (dates stored * P)
     int32_t n, N, W, store_all;
     uint32_t key0, key1;
+    int32_t k_begin, k_end;  // steps k_begin..k_end-1 (step k: date k to k + 1)
+    int32_t k_feat0;         // step whose date is feature index 0 (store_all)
+    int32_t ck_every;        // dates per window (0: no checkpoints)
+    int32_t ck_store;        // keep the state at the checkpoint dates
+    int32_t ck_slots;        // N + tasks of the pass
+    void* ckx;
+    void* ckv;
 };
 
 // Regression record of one (scenario, date): the inverse of the lower
@@ -126,18 +154,25 @@ struct RegRec {
 static_assert(sizeof(RegRec) == kRegRec * sizeof(double), "RegRec layout");
 
 struct LsmcArgs {
-    const void* feat;      // R2 planes [scen][date][path]
+    const void* feat;      // R2 planes [scen][date - f_date0][path]
     RegRec* reg;           // [scen][date] (date index k-1 for date k)
     const double* disc;    // [scen][n+1] exp(-r j dt), host libm
     const double* idisc;   // [scen][n+1] exp(+r j dt), host libm
     double* out;           // [scen][4]: price, se, skipped, itm-count
-    double* cf;            // [scen][P] (state in workspace), else null
+    double* cf;            // [scen][P] state in the workspace (cash flows, or
+                           // the cluster sweep's discounted cash flows between
+                           // windows), else null
     int32_t* tau;          // [scen][P] state / export, or null
     int64_t P;
     int64_t plane;
     int32_t n, m, cp, american;
     double K, inv_K, inv_tbar;
     int32_t export_tau, pad;
+    // dates of this launch: regressions k_lo..min(k_hi, n - 1); the first
+    // window (win_first, k_hi = n) starts the cash flows from the payoff at
+    // date n, the last (win_last, k_lo = 1) prices; features of date d sit
+    // at index d - f_date0 of each plane
+    int32_t k_lo, k_hi, f_date0, win_first, win_last, pad2;
 };
 
 // Cluster sweep: G workgroups of kClusterThreads cooperate on one scenario,

@@ -247,11 +247,14 @@ hs_status validate(const Request& q, int max_waves, uint32_t extra_flags)
         set_error("opts.sweep_mode = 1 needs n_paths <= %d", 16 * kSweepThreads);
         return HS_EINVAL;
     }
-    for (int i = 0; i < 2; ++i)
-        if (op.reserved[i] != 0) {
-            set_error("opts.reserved must be zero");
-            return HS_EINVAL;
-        }
+    if (op.reserved != 0) {
+        set_error("opts.reserved must be zero");
+        return HS_EINVAL;
+    }
+    if (op.window_dates < 0 || op.window_dates > q.n) {
+        set_error("opts.window_dates = %d outside 0..n_steps", op.window_dates);
+        return HS_EINVAL;
+    }
     if (op.scheme != HS_SCHEME_EULER_FT && op.scheme != HS_SCHEME_QE) {
         set_error("opts.scheme = %d", op.scheme);
         return HS_EINVAL;
@@ -375,7 +378,7 @@ Shape shape_of(const Request& q)
     sh.fp32 = q.opts.precision == HS_FP32_PATHS;
     sh.american = q.opt.style == HS_AMERICAN;
     sh.nmax = paths_nmax_bucket(q.N);
-    sh.tmax = paths_tmax(sh.fp32, sh.nmax);
+    sh.tmax = paths_tmax(sh.fp32, q.opts.scheme, sh.nmax);
     sh.feat = !sh.fp32 ? kFeatF64
               : q.opts.feature_format == HS_FEATURES_FP16 ? kFeatF16
               : q.opts.feature_format == HS_FEATURES_BF16 ? kFeatBF16
@@ -413,11 +416,13 @@ Shape shape_of(const Request& q)
     return sh;
 }
 
-Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, int n_groups)
+Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, int n_groups,
+                  int window)
 {
     const size_t R = sh.fp32 ? 4 : 8;
     const size_t P = static_cast<size_t>(q.P);
-    const size_t nd = sh.american ? static_cast<size_t>(q.n) : 1;
+    const size_t nd = !sh.american ? 1 : window > 0 ? static_cast<size_t>(window)
+                                                    : static_cast<size_t>(q.n);
     const size_t S = static_cast<size_t>(n_scen);
     Layout L;
     size_t off = 0;
@@ -446,6 +451,14 @@ Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, in
     if (sh.sweep == kSweepCluster)  // rows: dates 1..n-1, then the two price sums
         off = align_up(off + S * cluster_rows(sh.american, q.n) *
                                  static_cast<size_t>(sh.cluster_g) * kPartStride * sizeof(double));
+    // checkpoints of a windowed pass: every base asset and task, log price
+    // in R, variance in R (FP64 under QE)
+    const size_t ncp = static_cast<size_t>(checkpoint_count(q.n, sh.american ? window : 0));
+    const size_t slots = static_cast<size_t>(q.N + n_tasks);
+    L.ckx = off;
+    off = align_up(off + ncp * slots * P * R);
+    L.ckv = off;
+    off = align_up(off + ncp * slots * P * (q.opts.scheme == HS_SCHEME_QE ? 8 : R));
     L.feat = off;
     off = align_up(off + S * nd * P * feat_bytes(sh.feat));
     L.total = off;
@@ -657,14 +670,13 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
         }
     }
     pp.lay = layout_for(q, sh, static_cast<int>(pass.scen.size()), pp.ntasks,
-                        static_cast<int>(pp.groups.size()));
+                        static_cast<int>(pp.groups.size()), pass.window);
     return pp;
 }
 
 std::vector<Pass> make_passes(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,
                               size_t workspace_bytes, size_t* min_bytes)
 {
-    const int N = q.N;
     // units: {base + spots} and then each bumped scenario with its own path
     std::vector<std::vector<int>> units;
     std::vector<int> head{0};
@@ -673,38 +685,72 @@ std::vector<Pass> make_passes(const Request& q, const Shape& sh, const std::vect
     units.push_back(head);
     for (size_t i = 1; i < sc.size(); ++i)
         if (sc[i].kind >= 3) units.push_back({static_cast<int>(i)});
-    auto bytes_of = [&](int nscen, int ntask, int nunits) {
-        return layout_for(q, sh, nscen, ntask, nunits + 2 * kMaxWaves).total;
+    auto bytes_of = [&](int nscen, int ntask, int nunits, int window) {
+        return layout_for(q, sh, nscen, ntask, nunits + 2 * kMaxWaves, window).total;
+    };
+    auto tasks_of = [&](const std::vector<int>& u) {
+        int nt = 0;
+        for (int si : u) nt += sc[si].hi - sc[si].lo;
+        return nt;
+    };
+    // windows of dates: American only, and only where they save memory
+    const bool can_window = sh.american && q.n >= 2;
+    const int forced = can_window ? q.opts.window_dates : 0;
+    // the most dates per window with which unit u fits `limit` (0: none)
+    auto window_for = [&](const std::vector<int>& u, size_t limit) {
+        const int nt = tasks_of(u);
+        for (int c = q.n - 1; c >= 1; --c)
+            if (bytes_of(static_cast<int>(u.size()), nt, 1, c) <= limit) return c;
+        return 0;
     };
     size_t mn = 0;
     for (auto& u : units) {
-        int nt = 0;
-        for (int si : u) nt += sc[si].hi - sc[si].lo;
-        mn = std::max(mn, bytes_of(static_cast<int>(u.size()), nt, 1));
+        const int nt = tasks_of(u);
+        size_t best = forced > 0 ? bytes_of(static_cast<int>(u.size()), nt, 1, forced)
+                                 : bytes_of(static_cast<int>(u.size()), nt, 1, 0);
+        // the smallest footprint over window lengths: every length up to 64,
+        // then lengths about 5% apart (features grow with c, checkpoints
+        // shrink with it)
+        if (can_window && forced == 0)
+            for (int c = 1; c < q.n; c = c < 64 ? c + 1 : c + c / 20)
+                best = std::min(best, bytes_of(static_cast<int>(u.size()), nt, 1, c));
+        mn = std::max(mn, best);
     }
     if (min_bytes) *min_bytes = mn;
     std::vector<Pass> passes;
     if (workspace_bytes < mn) return passes;
     Pass cur;
     int cur_tasks = 0, cur_units = 0;
+    auto close = [&]() {
+        if (!cur.scen.empty()) passes.push_back(cur);
+        cur = Pass();
+        cur_tasks = 0;
+        cur_units = 0;
+    };
     for (size_t ui = 0; ui < units.size(); ++ui) {
-        int nt = 0;
-        for (int si : units[ui]) nt += sc[si].hi - sc[si].lo;
-        const size_t need = bytes_of(static_cast<int>(cur.scen.size() + units[ui].size()),
-                                     cur_tasks + nt, cur_units + 1);
-        if (!cur.scen.empty() && need > workspace_bytes) {
-            passes.push_back(cur);
-            cur = Pass();
-            cur_tasks = 0;
-            cur_units = 0;
+        const int nt = tasks_of(units[ui]);
+        const int us = static_cast<int>(units[ui].size());
+        const bool alone_fits = bytes_of(us, nt, 1, 0) <= workspace_bytes;
+        if (forced > 0 || !alone_fits) {
+            // a unit in windows of dates, in a pass of its own
+            close();
+            Pass wp;
+            wp.scen = units[ui];
+            wp.has_base_spot = ui == 0;
+            wp.window = forced > 0 ? forced : window_for(units[ui], workspace_bytes);
+            if (wp.window <= 0) return {};  // unreachable: mn covers every unit
+            passes.push_back(wp);
+            continue;
         }
+        const size_t need = bytes_of(static_cast<int>(cur.scen.size()) + us, cur_tasks + nt,
+                                     cur_units + 1, 0);
+        if (!cur.scen.empty() && need > workspace_bytes) close();
         if (ui == 0) cur.has_base_spot = true;
         for (int si : units[ui]) cur.scen.push_back(si);
         cur_tasks += nt;
         cur_units += 1;
     }
-    if (!cur.scen.empty()) passes.push_back(cur);
-    (void)N;
+    close();
     return passes;
 }
 

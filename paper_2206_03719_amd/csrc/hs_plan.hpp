@@ -2,6 +2,7 @@
 // (bump-and-revalue with common random numbers), the task/group tables of
 // the path kernel, and the workspace layout.  FP64 on the host throughout.
 #pragma once
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -53,17 +54,24 @@ int64_t num_scenarios(int N, uint32_t mask);
 // path precision).
 std::vector<unsigned char> model_table(const Request& q, const Scenario& base, bool fp32);
 
-// A pass runs a subset of scenarios whose features fit the workspace at once.
+// A pass runs a subset of scenarios whose features fit the workspace at once,
+// or one unit (base and spots, or one bumped scenario) in windows of `window`
+// dates with checkpoint-recompute of the paths (American only).
 struct Pass {
     std::vector<int> scen;  // canonical scenario indices, in plane order
     bool has_base_spot = false;
+    int window = 0;         // dates per window; 0 = all dates at once
 };
 
 // Byte offsets of a pass's regions inside the workspace.
 struct Layout {
     size_t base = 0, tasks = 0, groups = 0, disc = 0, reg = 0, out = 0, tau = 0, cf = 0,
-           sync = 0, part = 0, feat = 0, total = 0;
+           sync = 0, part = 0, ckx = 0, ckv = 0, feat = 0, total = 0;
 };
+
+// Checkpoints a pass in windows of c dates keeps: the states at dates
+// n - 2c, n - 3c, ... > 0.
+inline int checkpoint_count(int n, int c) { return c > 0 ? std::max(0, (n - 1) / c - 1) : 0; }
 
 // Backward-sweep variants.
 enum SweepKind { kSweepCluster = 0, kSweepBlockRegs = 1, kSweepBlockState = 2 };
@@ -80,7 +88,8 @@ struct Shape {
 };
 
 Shape shape_of(const Request& q);
-Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, int n_groups);
+Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, int n_groups,
+                  int window = 0);
 
 // Everything one pass uploads and launches.
 struct PassPlan {
@@ -95,8 +104,11 @@ struct PassPlan {
 // target_waves: waves the path kernel aims for; wmax: most waves per block.
 PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,
                    const Pass& pass, int target_waves, int wmax);
-// Splits the Greek set into passes that each fit `workspace_bytes`
-// (one pass if everything fits).  Empty result = even one unit does not fit.
+// Splits the Greek set into passes that each fit `workspace_bytes` (one pass
+// if everything fits); a unit that does not fit alone runs in windows of
+// dates (the most dates that fit), and opts.window_dates > 0 runs every unit
+// in windows of that many dates.  Empty result = even the smallest windows
+// do not fit; *min_bytes then holds the least workspace that works.
 std::vector<Pass> make_passes(const Request& q, const Shape& sh, const std::vector<Scenario>& sc,
                               size_t workspace_bytes, size_t* min_bytes);
 

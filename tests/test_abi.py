@@ -155,7 +155,10 @@ def test_scheme_validation():
     assert st == hs.EINVAL and "QE" in msg
     w2["model"]["rho"][1] = 0.0
     assert _call(w2, opts__scheme=1, ws_bytes=4096)[0] == hs.ENOMEM  # valid, tiny workspace
-    assert _call(w, opts__reserved=(ctypes.c_int32 * 2)(0, 1))[0] == hs.EINVAL
+    assert _call(w, opts__reserved=1)[0] == hs.EINVAL
+    assert _call(w, opts__window_dates=-1)[0] == hs.EINVAL
+    assert _call(w, opts__window_dates=17)[0] == hs.EINVAL  # n_steps = 16
+    assert _call(w, opts__window_dates=5, ws_bytes=4096)[0] == hs.ENOMEM
     assert _call(w, opts__feature_format=3)[0] == hs.EINVAL
     assert _call(w, opts__feature_format=1, precision="fp64")[0] == hs.EINVAL
     assert _call(w, opts__feature_format=2, opts__scheme=1)[0] == hs.EINVAL
