@@ -331,15 +331,14 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
                 return HS_EINVAL;
             }
         const int Sp = static_cast<int>(pass.scen.size());
-        HS_HIP(hipMemcpyAsync(ws + pp.lay.base, pp.base.data(), pp.base.size(),
-                              hipMemcpyHostToDevice, st), "upload base");
-        HS_HIP(hipMemcpyAsync(ws + pp.lay.tasks, pp.tasks.data(), pp.tasks.size(),
-                              hipMemcpyHostToDevice, st), "upload tasks");
-        HS_HIP(hipMemcpyAsync(ws + pp.lay.groups, pp.groups.data(),
-                              pp.groups.size() * sizeof(GroupP), hipMemcpyHostToDevice, st),
-               "upload groups");
-        HS_HIP(hipMemcpyAsync(ws + pp.lay.disc, pp.disc.data(), pp.disc.size() * sizeof(double),
-                              hipMemcpyHostToDevice, st), "upload discounts");
+        // the four parameter tables lead the workspace: one upload
+        std::vector<unsigned char> up(pp.lay.reg, 0);
+        std::memcpy(up.data() + pp.lay.base, pp.base.data(), pp.base.size());
+        std::memcpy(up.data() + pp.lay.tasks, pp.tasks.data(), pp.tasks.size());
+        std::memcpy(up.data() + pp.lay.groups, pp.groups.data(), pp.groups.size() * sizeof(GroupP));
+        std::memcpy(up.data() + pp.lay.disc, pp.disc.data(), pp.disc.size() * sizeof(double));
+        HS_HIP(hipMemcpyAsync(ws, up.data(), up.size(), hipMemcpyHostToDevice, st),
+               "upload tables");
 
         PassLaunch L;
         // zero padding too: the graph cache keys on these bytes
@@ -408,8 +407,9 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         if (L.cluster) {
             // a Greek set that one workgroup per CU holds keeps the basis values
             // in registers; a larger one fits two workgroups per CU without
-            L.keep = static_cast<int64_t>(Sp) * sh.cluster_g <= kPlanComputeUnits;
-            cap = cluster_capacity(sh.feat, sh.cluster_q, L.keep,
+            // (windows run the variant without kept values)
+            L.keep = L.window == 0 && static_cast<int64_t>(Sp) * sh.cluster_g <= kPlanComputeUnits;
+            cap = cluster_capacity(sh.feat, sh.cluster_q, L.keep, L.window > 0,
                                    cluster_lds_bytes(q.n, sh.cluster_g));
             if (cap < sh.cluster_g) {
                 if (q.opts.sweep_mode == 3) {
@@ -439,12 +439,11 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         else
             HS_HIP(enqueue_pass(L, st, timing ? ev : nullptr), "kernel launch");
 
-        std::vector<double> out(static_cast<size_t>(Sp) * 4);
-        int32_t err_host = 0;
-        HS_HIP(hipMemcpyAsync(out.data(), la.out, out.size() * sizeof(double),
+        // results [Sp][4] and the status flag right after them: one copy
+        std::vector<double> out(static_cast<size_t>(Sp) * 4 + 1);
+        HS_HIP(hipMemcpyAsync(out.data(), la.out, static_cast<size_t>(Sp) * 4 * sizeof(double) +
+                                                     sizeof(int32_t),
                               hipMemcpyDeviceToHost, st), "download results");
-        HS_HIP(hipMemcpyAsync(&err_host, L.err_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st),
-               "download sweep status");
         std::vector<int32_t> tau;
         if (la.export_tau) {
             tau.resize(static_cast<size_t>(Sp) * q.P);
@@ -453,6 +452,8 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         }
         HS_HIP(hipStreamSynchronize(st), "stream synchronize");
         if (cluster_lock.owns_lock()) cluster_lock.unlock();
+        int32_t err_host = 0;
+        std::memcpy(&err_host, out.data() + static_cast<size_t>(Sp) * 4, sizeof(int32_t));
         if (err_host != 0) {
             set_error("cluster sweep: a workgroup wait timed out (device oversubscribed?)");
             return HS_EDEVICE;

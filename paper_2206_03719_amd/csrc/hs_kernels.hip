@@ -271,16 +271,14 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 
     // checkpoint-recompute: the state at date n - (i + 2) c, checkpoint i,
     // lives at [(i slots + slot) P + p]; the base assets are kept by block
-    // group 0 and read by every group, a task by the wave that owns it
-    R* const ckx = static_cast<R*>(A.ckx);
-    VT* const ckv = static_cast<VT*>(A.ckv);
-    // (one lane pointer per array and wave-uniform slot offsets; compiled in
-    // only for windowed passes, CK)
-    if (CK && A.k_begin > 0 && live) {
+    // group 0 and read by every group, a task by the wave that owns it (one
+    // lane pointer per array and wave-uniform slot offsets; compiled in only
+    // for windowed passes, CK)
+    if constexpr (CK) if (A.k_begin > 0 && live) {
         const int64_t row0 =
             static_cast<int64_t>((A.n - A.k_begin) / A.ck_every - 2) * A.ck_slots;
-        const R* const bx = ckx + row0 * P + p;
-        const VT* const bv = ckv + row0 * P + p;
+        const R* const bx = static_cast<const R*>(A.ckx) + row0 * P + p;
+        const VT* const bv = static_cast<const VT*>(A.ckv) + row0 * P + p;
 #pragma unroll
         for (int i = 0; i < kOwnPerWave; ++i) {
             const int a = w + i * W;
@@ -299,7 +297,7 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
         }
     }
 
-    for (int k = A.k_begin; k < A.k_end; ++k) {
+    for (int k = CK ? A.k_begin : 0; k < (CK ? A.k_end : A.n); ++k) {
         R* const buf = lds + (k & 1) * 5 * SLAB;
         R* const s_eps = buf;
         VT* const s_eta = SCHEME == HS_SCHEME_QE ? lds_eta + (k & 1) * SLAB
@@ -356,8 +354,11 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
         __syncthreads();
 
         // 3) features
-        const bool store = A.store_all ? k >= A.k_feat0 : k == A.n - 1;
-        const int64_t off = (A.store_all ? static_cast<int64_t>(k - A.k_feat0) * P : 0) + p;
+        // (checkpoint runs store the dates from k_feat0 + 1 on, at index 0)
+        const bool store = CK ? (A.store_all ? k >= A.k_feat0 : k == A.n - 1)
+                              : (A.store_all || k == A.n - 1);
+        const int64_t off =
+            (A.store_all ? static_cast<int64_t>(CK ? k - A.k_feat0 : k) * P : 0) + p;
         R eps[NMAX], E[NMAX], Sb[NMAX], vpb[NMAX], pm[NMAX], sm[NMAX], ps[NMAX];
 #pragma unroll
         for (int a = 0; a < NMAX; ++a) {
@@ -466,12 +467,12 @@ __global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
 
         // 5) the state at a checkpoint date (where a window other than the
         //    last two dates' windows starts over)
-        const int d = k + 1;
-        if (CK && A.ck_store && (A.n - d) % A.ck_every == 0 && (A.n - d) / A.ck_every >= 2 &&
-            live) {
-            const int64_t row0 = static_cast<int64_t>((A.n - d) / A.ck_every - 2) * A.ck_slots;
-            R* const bx = ckx + row0 * P + p;
-            VT* const bv = ckv + row0 * P + p;
+        if constexpr (CK) if (A.ck_store && (A.n - k - 1) % A.ck_every == 0 &&
+                              (A.n - k - 1) / A.ck_every >= 2 && live) {
+            const int64_t row0 =
+                static_cast<int64_t>((A.n - k - 1) / A.ck_every - 2) * A.ck_slots;
+            R* const bx = static_cast<R*>(A.ckx) + row0 * P + p;
+            VT* const bv = static_cast<VT*>(A.ckv) + row0 * P + p;
             if (blockIdx.y == 0) {
 #pragma unroll
                 for (int i = 0; i < kOwnPerWave; ++i) {
@@ -1240,11 +1241,10 @@ __device__ __forceinline__ bool cluster_exchange(double (&b)[K], int m, double* 
 // decision recomputes them from that date's features, within 128 registers so
 // that two workgroups share a CU (4 waves per SIMD), for Greek sets larger
 // than one workgroup per CU can hold.  Both give the same numbers.
-template <typename R, int Q, bool KEEP>
+template <typename R, int Q, bool KEEP, bool WIN>
 __global__ void __launch_bounds__(kClusterThreads,
                                   (!KEEP && Q <= cluster_qmax_shared(sizeof(R) <= 4)) ? 4 : 2)
-    k_sweep_cluster(const LsmcArgs A,
-                                                                   const ClusterArgs C)
+    k_sweep_cluster(const LsmcArgs A, const ClusterArgs C)
 {
     extern __shared__ unsigned char hs_smem[];
     constexpr int NW = kClusterThreads / 64;
@@ -1272,11 +1272,13 @@ __global__ void __launch_bounds__(kClusterThreads,
     const cptr<double> dsc = as_const<double>(A.disc) + static_cast<int64_t>(s) * (n + 1);
     const cptr<double> idsc = as_const<double>(A.idisc) + static_cast<int64_t>(s) * (n + 1);
     const int64_t pbase = static_cast<int64_t>(g) * (kClusterThreads * Q) + threadIdx.x;
-    const int f0 = A.f_date0;
-    const int64_t last = static_cast<int64_t>(n - f0) * P;  // date n
-    const int k_lo = A.k_lo;
-    const int k_top = min(A.k_hi, n - 1);  // first regression date of this launch
-    double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase;
+    // a window of dates (WIN), else every date: regressions k_top..k_lo, the
+    // features of date d at index d - f0
+    const int f0 = WIN ? A.f_date0 : 1;
+    const int64_t last = WIN ? static_cast<int64_t>(n - f0) * P  // date n
+                             : (A.american ? static_cast<int64_t>(n - 1) * P : 0);
+    const int k_lo = WIN ? A.k_lo : 1;
+    const int k_top = WIN ? min(A.k_hi, n - 1) : n - 1;
     int par = 0;
 
     // State per path: the cash flow discounted to time 0, D = h_tau exp(-r tau
@@ -1293,7 +1295,7 @@ __global__ void __launch_bounds__(kClusterThreads,
     // (a window after the first takes D from the workspace, where the
     // previous window left it)
     double D[Q];
-    if (A.win_first) {
+    if (!WIN || A.win_first) {
         const double dn = dsc[n];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -1302,6 +1304,7 @@ __global__ void __launch_bounds__(kClusterThreads,
             if (tau && i < nlive) tau[i * kClusterThreads] = n;
         }
     } else {
+        const double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase;
 #pragma unroll
         for (int i = 0; i < Q; ++i) D[i] = i < nlive ? dstate[i * kClusterThreads] : 0.0;
     }
@@ -1477,7 +1480,8 @@ __global__ void __launch_bounds__(kClusterThreads,
         }
     }
 
-    if (!A.win_last) {  // a window before the last: D waits in the workspace
+    if (WIN && !A.win_last) {  // a window before the last: D waits in the workspace
+        double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             if (i < nlive) dstate[i * kClusterThreads] = D[i];
@@ -1512,7 +1516,7 @@ __global__ void __launch_bounds__(kClusterThreads,
         double* o = A.out + static_cast<int64_t>(s) * 4;
         o[0] = mean;
         o[1] = sqrt(s2[0] / static_cast<double>(P - 1) / static_cast<double>(P));
-        o[2] = (A.win_first ? 0.0 : o[2]) + skipped;
+        o[2] = WIN && !A.win_first ? o[2] + skipped : skipped;
         o[3] = 0.0;
     }
 }
@@ -1648,25 +1652,25 @@ hipError_t launch_sweep_r(int q, const LsmcArgs& a, int S, hipStream_t st)
     }
 }
 
-template <typename R, int Q, bool KEEP>
+template <typename R, int Q, bool KEEP, bool WIN>
 hipError_t launch_cluster_t(const LsmcArgs& a, const ClusterArgs& c, int S_launch, size_t lds,
                             hipStream_t st)
 {
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, KEEP>),
+            reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, KEEP, WIN>),
             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_sweep_cluster<R, Q, KEEP>), dim3(S_launch * c.G),
+    hipLaunchKernelGGL((k_sweep_cluster<R, Q, KEEP, WIN>), dim3(S_launch * c.G),
                        dim3(kClusterThreads), lds, st, a, c);
     return hipGetLastError();
 }
 
-template <typename R, int Q, bool KEEP>
+template <typename R, int Q, bool KEEP, bool WIN>
 int cluster_capacity_t(size_t lds)
 {
-    const void* f = reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, KEEP>);
+    const void* f = reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, KEEP, WIN>);
     if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(lds)) != hipSuccess)
         return 0;
@@ -1689,14 +1693,17 @@ size_t cluster_lds_bytes(int n, int G)
     return sizeof(double) * (2 * (kClusterThreads / 64) * kPartStride + 2 * kPartStride) + 16;
 }
 
-int cluster_capacity(int ft, int q, bool keep, size_t lds)
+int cluster_capacity(int ft, int q, bool keep, bool win, size_t lds)
 {
+    if (keep && win) return 0;  // windows run the variant without kept basis values
     return with_feat(ft, 0, [&](auto tag) -> int {
         using FT = std::remove_pointer_t<decltype(tag)>;
         switch (q) {
-#define HS_CAP(Q)                                                                        \
-    case Q:                                                                              \
-        return keep ? cluster_capacity_t<FT, Q, true>(lds) : cluster_capacity_t<FT, Q, false>(lds);
+#define HS_CAP(Q)                                                                          \
+    case Q:                                                                                \
+        return keep  ? cluster_capacity_t<FT, Q, true, false>(lds)                         \
+               : win ? cluster_capacity_t<FT, Q, false, true>(lds)                         \
+                     : cluster_capacity_t<FT, Q, false, false>(lds);
             HS_CAP(1) HS_CAP(2) HS_CAP(3) HS_CAP(4) HS_CAP(5) HS_CAP(6) HS_CAP(7) HS_CAP(8)
 #undef HS_CAP
         default: return 0;
@@ -1708,13 +1715,17 @@ hipError_t launch_sweep_cluster(int ft, int q, bool keep, const LsmcArgs& a,
                                 const ClusterArgs& c, int S_launch, hipStream_t st)
 {
     const size_t lds = cluster_lds_bytes(a.n, c.G);
+    const bool win = a.k_lo != 1 || a.k_hi != a.n || !a.win_first || !a.win_last;
+    if (win && (keep || !a.american || !a.cf || a.k_lo < 1 || a.k_hi > a.n || a.f_date0 > a.k_lo))
+        return hipErrorInvalidValue;
     return with_feat(ft, hipErrorInvalidValue, [&](auto tag) -> hipError_t {
         using FT = std::remove_pointer_t<decltype(tag)>;
         switch (q) {
-#define HS_LAUNCH(Q)                                                             \
-    case Q:                                                                      \
-        return keep ? launch_cluster_t<FT, Q, true>(a, c, S_launch, lds, st)     \
-                    : launch_cluster_t<FT, Q, false>(a, c, S_launch, lds, st);
+#define HS_LAUNCH(Q)                                                                    \
+    case Q:                                                                             \
+        return keep  ? launch_cluster_t<FT, Q, true, false>(a, c, S_launch, lds, st)    \
+               : win ? launch_cluster_t<FT, Q, false, true>(a, c, S_launch, lds, st)    \
+                     : launch_cluster_t<FT, Q, false, false>(a, c, S_launch, lds, st);
             HS_LAUNCH(1) HS_LAUNCH(2) HS_LAUNCH(3) HS_LAUNCH(4) HS_LAUNCH(5) HS_LAUNCH(6)
             HS_LAUNCH(7) HS_LAUNCH(8)
 #undef HS_LAUNCH

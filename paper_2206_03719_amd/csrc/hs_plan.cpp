@@ -437,16 +437,17 @@ Layout layout_for(const Request& q, const Shape& sh, int n_scen, int n_tasks, in
     off = align_up(off + 2 * S * (q.n + 1) * sizeof(double));
     L.reg = off;
     off = align_up(off + (sh.american ? S * q.n * sizeof(RegRec) : 0));
+    // the results and the status flag side by side: one copy back per pass
     L.out = off;
-    off = align_up(off + S * 4 * sizeof(double));
+    off = off + S * 4 * sizeof(double);
+    L.sync = off;
+    off = align_up(off + (S + 64) * sizeof(uint32_t));
     // exercise dates and cash flows of the workspace-state sweep (also the
     // fallback when a cluster does not fit the device) and the exported dates
     L.tau = off;
     off = align_up(off + S * P * sizeof(int32_t));
     L.cf = off;
     off = align_up(off + S * P * sizeof(double));
-    L.sync = off;
-    off = align_up(off + (S + 64) * sizeof(uint32_t));
     L.part = off;
     if (sh.sweep == kSweepCluster)  // rows: dates 1..n-1, then the two price sums
         off = align_up(off + S * cluster_rows(sh.american, q.n) *

@@ -197,3 +197,22 @@ def test_path_features_validation():
 def test_greek_set_kernel_flag_only_for_path_features():
     w = W.best_of_call(n_paths=1000, n_steps=16)
     assert _call(w, flags=hs.FLAG_GREEK_SET_KERNEL)[0] == hs.EINVAL
+
+
+def test_window_workspace_sizes():
+    # windows of dates (checkpoint-recompute) lower the smallest workspace far
+    # below one unit's features; forced windows size every unit in them
+    w = W.best_of_call()
+    full = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"])
+    mn = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"], minimum=True)
+    head_unit = 11 * 252 * 25000 * 8  # base and spot scenarios' features alone
+    assert mn < head_unit / 8
+    w16 = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"], window_dates=16)
+    assert mn <= w16 < full / 10
+    # one window of every date is one pass over all dates
+    wall = hs.workspace_bytes(w["model"], w["option"], 25000, 252, w["bumps"], window_dates=252)
+    assert head_unit < wall < full
+    # European options never use windows
+    eu = dict(w["option"], style="european")
+    assert (hs.workspace_bytes(w["model"], eu, 25000, 252, w["bumps"], window_dates=16) ==
+            hs.workspace_bytes(w["model"], eu, 25000, 252, w["bumps"], minimum=True))
