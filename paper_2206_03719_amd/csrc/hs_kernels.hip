@@ -867,16 +867,13 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const LsmcArgs A)
 #pragma unroll
     for (int i = 0; i < 12; ++i) S[i] = 0.0;
     for (int64_t p0 = threadIdx.x; p0 < P; p0 += kGramThreads * U1) {
+        // every load issues, with no branch between them (a path past P
+        // reads the last path and is masked below), so all U1 are in flight
         R2<R> f[U1];
 #pragma unroll
         for (int u = 0; u < U1; ++u) {
             const int64_t p = p0 + u * kGramThreads;
-            if (p < P) {
-                f[u] = F[p];
-            } else {
-                f[u].u = R(0);
-                f[u].a = R(0);
-            }
+            f[u] = F[p < P ? p : P - 1];
         }
 #pragma unroll
         for (int u = 0; u < U1; ++u) {
@@ -1243,7 +1240,8 @@ __device__ __forceinline__ bool cluster_exchange(double (&b)[K], int m, double* 
 // than one workgroup per CU can hold.  Both give the same numbers.
 template <typename R, int Q, bool KEEP, bool WIN>
 __global__ void __launch_bounds__(kClusterThreads,
-                                  (!KEEP && Q <= cluster_qmax_shared(sizeof(R) <= 4)) ? 4 : 2)
+                                  (!KEEP && !WIN && Q <= cluster_qmax_shared(sizeof(R) <= 4)) ? 4
+                                                                                             : 2)
     k_sweep_cluster(const LsmcArgs A, const ClusterArgs C)
 {
     extern __shared__ unsigned char hs_smem[];
@@ -1313,11 +1311,13 @@ __global__ void __launch_bounds__(kClusterThreads,
     bool have = false;  // beta of the later date k+1 is valid
     double skipped = 0.0;
     if (A.american) {
-        // cu/ca: features of date k (this iteration's regression); nu/na: date
-        // k-1, loaded one iteration ago; fu/fa: date k-2, loaded after this
-        // iteration's exchange (without KEEP: date k+1 until its decision is
-        // taken, then date k-2).
-        R cu[Q], ca[Q], nu[Q], na[Q], fu[Q], fa[Q];
+        // Three feature buffers take turns: at date k, cur holds date k (this
+        // regression), nxt date k-1 (loaded one date ago) and old date k+1
+        // (without KEEP, its decision's features); after the exchange old
+        // receives date k-2.  The loop is unrolled three times so the roles
+        // rotate by renaming and a load's destination is not read until two
+        // dates later: the loads fly across the next date's work.
+        R bu[3][Q], ba[3][Q];
         // payoff and centred basis variables of each path at the date last
         // regressed, kept for that date's exercise decision (h = 0: out of
         // the money, no decision)
@@ -1325,24 +1325,23 @@ __global__ void __launch_bounds__(kClusterThreads,
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int64_t p = pbase + i * kClusterThreads;
-            cu[i] = R(0);
-            ca[i] = R(0);
-            nu[i] = R(0);
-            na[i] = R(0);
-            fu[i] = R(0);
-            fa[i] = R(0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                bu[j][i] = R(0);
+                ba[j][i] = R(0);
+            }
             hh[i] = 0.0;
             xx[i] = 0.0;
             ww[i] = 0.0;
             if (i < nlive && k_top >= k_lo) {
                 const R2<R> f = F[static_cast<int64_t>(k_top - f0) * P + p];
-                cu[i] = f.u;
-                ca[i] = f.a;
+                bu[0][i] = f.u;
+                ba[0][i] = f.a;
             }
             if (i < nlive && k_top - 1 >= k_lo) {
                 const R2<R> f = F[static_cast<int64_t>(k_top - 1 - f0) * P + p];
-                nu[i] = f.u;
-                na[i] = f.a;
+                bu[1][i] = f.u;
+                ba[1][i] = f.a;
             }
         }
         // regression-set flag and means of date k, loaded one date ahead
@@ -1350,7 +1349,40 @@ __global__ void __launch_bounds__(kClusterThreads,
         double r_cU = k_top >= k_lo ? recs[k_top - 1].cU : 0.0;
         double r_cA = k_top >= k_lo ? recs[k_top - 1].cA : 0.0;
         double bcU = 0.0, bcA = 0.0;  // regression-set means of date k+1
-        for (int k = k_top; k >= k_lo; --k) {
+
+        // the exercise decision at date kd with the regression of that date
+        // (beta, bcU, bcA), from the kept values or from that date's features
+        auto decide = [&](int kd, const R (&du)[Q], const R (&da)[Q]) {
+            const double d1 = dsc[kd];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                double h, x, w;
+                if constexpr (KEEP) {
+                    h = hh[i];
+                    x = xx[i];
+                    w = ww[i];
+                } else {
+                    const double U = static_cast<double>(du[i]);
+                    h = i < nlive ? payoff(A.cp, A.K, U) : 0.0;
+                    double phi[5];
+                    basis(m, U, static_cast<double>(da[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
+                    x = phi[1];
+                    w = phi[3];
+                }
+                if (h > 0.0) {
+                    const double cont = beta[0] + beta[1] * x + beta[2] * (x * x) + beta[3] * w +
+                                        beta[4] * (x * w);
+                    if (h > cont) {
+                        D[i] = h * d1;
+                        if (tau) tau[i * kClusterThreads] = kd;
+                    }
+                }
+            }
+        };
+
+        // one date k with buffers cur = C, old = O; false if a wait timed out
+        auto step = [&](int k, auto Ci, auto Oi) -> bool {
+            constexpr int CB = decltype(Ci)::value, OB = decltype(Oi)::value;
             const bool ok = r_ok != 0.0;
             const double cU = r_cU, cA = r_cA;
             if (k > k_lo) {
@@ -1358,43 +1390,21 @@ __global__ void __launch_bounds__(kClusterThreads,
                 r_cU = recs[k - 2].cU;
                 r_cA = recs[k - 2].cA;
             }
-            const double d1 = dsc[k + 1], ik = idsc[k];
-            // per path: exercise at date k+1 with its regression (from the
-            // values kept at its regression), then this date's right-hand
-            // side with the updated cash flow
+            const double ik = idsc[k];
+            // exercise at date k+1 with its regression, then this date's
+            // right-hand side with the updated cash flows
+            if (have) decide(k + 1, bu[OB], ba[OB]);
             double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                if (have) {
-                    double h, x, w;
-                    if constexpr (KEEP) {
-                        h = hh[i];
-                        x = xx[i];
-                        w = ww[i];
-                    } else {
-                        const double U = static_cast<double>(fu[i]);
-                        h = i < nlive ? payoff(A.cp, A.K, U) : 0.0;
-                        double phi[5];
-                        basis(m, U, static_cast<double>(fa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
-                        x = phi[1];
-                        w = phi[3];
-                    }
-                    if (h > 0.0) {
-                        const double cont = beta[0] + beta[1] * x + beta[2] * (x * x) +
-                                            beta[3] * w + beta[4] * (x * w);
-                        if (h > cont) {
-                            D[i] = h * d1;
-                            if (tau) tau[i * kClusterThreads] = k + 1;
-                        }
-                    }
-                }
                 if constexpr (KEEP) hh[i] = 0.0;
                 if (ok) {
-                    const double U = static_cast<double>(cu[i]);
+                    const double U = static_cast<double>(bu[CB][i]);
                     const double h = payoff(A.cp, A.K, U);
                     if (i < nlive && h > 0.0) {
                         double phi[5];
-                        basis(m, U, static_cast<double>(ca[i]), cU, cA, A.inv_K, A.inv_tbar, phi);
+                        basis(m, U, static_cast<double>(ba[CB][i]), cU, cA, A.inv_K, A.inv_tbar,
+                              phi);
                         const double Y = D[i] * ik;
 #pragma unroll
                         for (int q = 0; q < 5; ++q)
@@ -1414,7 +1424,7 @@ __global__ void __launch_bounds__(kClusterThreads,
                 for (int i = 0; i < 15; ++i) Lk[i] = recs[k - 1].L[i];
                 if (!cluster_exchange<5>(b, m, part + static_cast<int64_t>(k) * row_len, G, g, par,
                                          C, Ls))
-                    return;
+                    return false;
                 par ^= 1;
                 solve_packed(m, Lk, b, beta);
                 bcU = cU;
@@ -1424,58 +1434,40 @@ __global__ void __launch_bounds__(kClusterThreads,
                 skipped += 1.0;
                 have = false;
             }
-            // date k-2 for two iterations on, issued after the exchange, whose
-            // slot polls would otherwise wait for these loads (vector loads
-            // complete in order)
+            // date k-2 into old, issued after the exchange, whose slot polls
+            // would otherwise wait for these loads (vector loads complete in
+            // order)
+            // (all Q loads issue without branches: a path past P reads the
+            // last path, whose value no decision or sum uses)
             if (k - 2 >= k_lo) {
                 const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 2 - f0) * P;
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    if (i < nlive) {
-                        const R2<R> f = Fn[pbase + i * kClusterThreads];
-                        fu[i] = f.u;
-                        fa[i] = f.a;
-                    }
+                    const int64_t p = pbase + i * kClusterThreads;
+                    const R2<R> f = Fn[p < P ? p : P - 1];
+                    bu[OB][i] = f.u;
+                    ba[OB][i] = f.a;
                 }
             }
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const R tu = fu[i], ta = fa[i];
-                if constexpr (!KEEP) {  // date k becomes the decision date
-                    fu[i] = cu[i];
-                    fa[i] = ca[i];
-                }
-                cu[i] = nu[i];
-                ca[i] = na[i];
-                nu[i] = tu;
-                na[i] = ta;
-            }
+            return true;
+        };
+
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        for (int k = k_top; k >= k_lo;) {
+            if (!step(k, I0{}, I2{})) return;
+            if (--k < k_lo) break;
+            if (!step(k, I1{}, I0{})) return;
+            if (--k < k_lo) break;
+            if (!step(k, I2{}, I1{})) return;
+            --k;
         }
-        if (have) {  // exercise at date k_lo (1 in the last window)
-            const double d1 = dsc[k_lo];
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                double h, x, w;
-                if constexpr (KEEP) {
-                    h = hh[i];
-                    x = xx[i];
-                    w = ww[i];
-                } else {
-                    const double U = static_cast<double>(fu[i]);
-                    h = i < nlive ? payoff(A.cp, A.K, U) : 0.0;
-                    double phi[5];
-                    basis(m, U, static_cast<double>(fa[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
-                    x = phi[1];
-                    w = phi[3];
-                }
-                if (h > 0.0) {
-                    const double cont = beta[0] + beta[1] * x + beta[2] * (x * x) + beta[3] * w +
-                                        beta[4] * (x * w);
-                    if (h > cont) {
-                        D[i] = h * d1;
-                        if (tau) tau[i * kClusterThreads] = k_lo;
-                    }
-                }
+        if (have) {  // exercise at date k_lo (1 in the last window): its buffer was cur last
+            switch ((k_top - k_lo) % 3) {
+            case 0: decide(k_lo, bu[0], ba[0]); break;
+            case 1: decide(k_lo, bu[1], ba[1]); break;
+            default: decide(k_lo, bu[2], ba[2]); break;
             }
         }
     }

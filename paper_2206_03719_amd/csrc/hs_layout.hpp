@@ -183,7 +183,7 @@ constexpr int kMaxClusterGroups = 1024;
 constexpr int kPlanComputeUnits = 256;  // MI355X: the cluster sweep plans for this many CUs
 // Most paths per thread with which a workgroup of the cluster sweep that does
 // not keep basis values fits 128 registers (two workgroups per CU).
-constexpr int cluster_qmax_shared(bool fp32) { return fp32 ? 7 : 4; }
+constexpr int cluster_qmax_shared(bool fp32) { return fp32 ? 6 : 4; }
 
 // Partial slots start as kEmptySlot (a NaN bit pattern that arithmetic never
 // produces); a workgroup's published partial is the slot's only write.
