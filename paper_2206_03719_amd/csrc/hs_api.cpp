@@ -280,9 +280,10 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
     hs_status rc = expand_scenarios(q, sc);
     if (rc != HS_OK) return rc;
     const Shape sh = shape_of(q);
-    size_t mn = 0;
-    const std::vector<Pass> passes = make_passes(q, sh, sc, ws_bytes, &mn);
+    const std::vector<Pass> passes = make_passes(q, sh, sc, ws_bytes, nullptr);
     if (passes.empty()) {
+        size_t mn = 0;
+        (void)make_passes(q, sh, sc, 0, &mn);
         set_error("workspace of %zu bytes is below the minimum of %zu", ws_bytes, mn);
         return HS_ENOMEM;
     }

@@ -659,15 +659,27 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
         fill_tables<double>(q, sh, sc, pass, gs, pp);
     // discount factors exp(-r j dt), j = 0..n, per scenario of the pass, then
     // their inverses exp(+r j dt)
+    // (scenarios with the same r and T share their rows: computed once)
     const int n = q.n;
     const size_t ns = pass.scen.size();
-    pp.disc.resize(2 * ns * (n + 1));
+    const size_t row = static_cast<size_t>(n) + 1;
+    pp.disc.resize(2 * ns * row);
     for (size_t i = 0; i < ns; ++i) {
         const Scenario& s = sc[pass.scen[i]];
+        size_t same = i;
+        for (size_t h = 0; h < i && same == i; ++h) {
+            const Scenario& t = sc[pass.scen[h]];
+            if (t.r == s.r && t.T == s.T) same = h;
+        }
+        if (same != i) {
+            std::copy_n(pp.disc.begin() + same * row, row, pp.disc.begin() + i * row);
+            std::copy_n(pp.disc.begin() + (ns + same) * row, row, pp.disc.begin() + (ns + i) * row);
+            continue;
+        }
         const double dt = s.T / static_cast<double>(n);
         for (int j = 0; j <= n; ++j) {
-            pp.disc[i * (n + 1) + j] = std::exp(-s.r * static_cast<double>(j) * dt);
-            pp.disc[(ns + i) * (n + 1) + j] = std::exp(s.r * static_cast<double>(j) * dt);
+            pp.disc[i * row + j] = std::exp(-s.r * static_cast<double>(j) * dt);
+            pp.disc[(ns + i) * row + j] = std::exp(s.r * static_cast<double>(j) * dt);
         }
     }
     pp.lay = layout_for(q, sh, static_cast<int>(pass.scen.size()), pp.ntasks,
@@ -704,18 +716,27 @@ std::vector<Pass> make_passes(const Request& q, const Shape& sh, const std::vect
             if (bytes_of(static_cast<int>(u.size()), nt, 1, c) <= limit) return c;
         return 0;
     };
-    size_t mn = 0;
-    for (auto& u : units) {
-        const int nt = tasks_of(u);
-        size_t best = forced > 0 ? bytes_of(static_cast<int>(u.size()), nt, 1, forced)
-                                 : bytes_of(static_cast<int>(u.size()), nt, 1, 0);
-        // the smallest footprint over window lengths: every length up to 64,
-        // then lengths about 5% apart (features grow with c, checkpoints
-        // shrink with it)
-        if (can_window && forced == 0)
-            for (int c = 1; c < q.n; c = c < 64 ? c + 1 : c + c / 20)
-                best = std::min(best, bytes_of(static_cast<int>(u.size()), nt, 1, c));
-        mn = std::max(mn, best);
+    // each unit alone, all dates at once
+    size_t unit_max = 0;
+    for (auto& u : units)
+        unit_max = std::max(unit_max, bytes_of(static_cast<int>(u.size()), tasks_of(u), 1, 0));
+    // the least workspace that works (only computed when asked for, or when
+    // some unit needs windows of dates)
+    size_t mn = unit_max;
+    if (min_bytes || forced > 0 || workspace_bytes < unit_max) {
+        mn = 0;
+        for (auto& u : units) {
+            const int nt = tasks_of(u);
+            size_t best = forced > 0 ? bytes_of(static_cast<int>(u.size()), nt, 1, forced)
+                                     : bytes_of(static_cast<int>(u.size()), nt, 1, 0);
+            // the smallest footprint over window lengths: every length up to
+            // 64, then lengths about 5% apart (features grow with c,
+            // checkpoints shrink with it)
+            if (can_window && forced == 0)
+                for (int c = 1; c < q.n; c = c < 64 ? c + 1 : c + c / 20)
+                    best = std::min(best, bytes_of(static_cast<int>(u.size()), nt, 1, c));
+            mn = std::max(mn, best);
+        }
     }
     if (min_bytes) *min_bytes = mn;
     std::vector<Pass> passes;
