@@ -604,8 +604,12 @@ hs_status hs_autotune(const hs_model* model, const double* corr, const hs_option
     q.opts.flags &= ~(HS_FLAG_TIMING | HS_FLAG_EXPORT_TAU | HS_FLAG_GRAPH);
     q.opts.waves_per_block = 0;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    static const int waves[] = {1024, 2048, 4096, 8192};
-    static const int wmaxes[] = {4, 8};
+    // target waves (the default first) x the most waves per block (1: as
+    // few as the base assets allow); measured on the 5- and 10-asset sets,
+    // the best shape ranges from 8 waves per block at 25k paths to 3 at
+    // 200k paths with 10 assets
+    const int waves[] = {default_target_waves(), 1024, 8192};
+    static const int wmaxes[] = {1, 2, 3, 4, 6, 8};
     Tune best{};
     double best_t = 1e300;
     for (int tw : waves)
