@@ -221,7 +221,10 @@ size_t hs_workspace_bytes(const hs_model *model, const hs_option *option, int64_
                           int32_t n_steps, const hs_bumps *bumps, const hs_opts *opts);
 
 /* Smallest workspace hs_price_greeks accepts; it then runs the Greek set in
- * several passes over scenario groups (same results, bit for bit). */
+ * several passes over scenario groups and, where one group's features do not
+ * fit, in windows of dates that recompute the paths from checkpoints of their
+ * state (same results, bit for bit).  With opts.window_dates > 0 both calls
+ * size every group in windows of that many dates. */
 size_t hs_workspace_min_bytes(const hs_model *model, const hs_option *option, int64_t n_paths,
                               int32_t n_steps, const hs_bumps *bumps, const hs_opts *opts);
 
