@@ -162,7 +162,8 @@ typedef struct hs_bumps {
 typedef struct hs_opts {
     int32_t precision;       /* HS_FP64 | HS_FP32_PATHS                          */
     int32_t waves_per_block; /* path kernel: 0 = planner's choice, else 1..8 waves
-                                of 64 paths' scenario groups per block             */
+                                of 64 paths' scenario groups per block (FP64 at
+                                13-16 assets runs at most 4)                       */
     uint64_t seed;           /* Philox key                                         */
     uint32_t flags;          /* HS_FLAG_*                                          */
     int32_t sweep_mode;      /* backward sweep: 0 = automatic (cluster when it fits the

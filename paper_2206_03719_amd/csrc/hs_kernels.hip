@@ -218,7 +218,8 @@ __device__ __forceinline__ void qe_step(CP c, R zx, double zv, R& X, double& v)
 // max(v, 0), each [asset][lane]; under QE the variance normal eta and the
 // variance state are FP64 (VT) in both path precisions.
 template <typename R, int NMAX, int TMAX, int SCHEME, typename FT, bool CK>
-__global__ void __launch_bounds__(kLanes * kMaxWaves) k_paths(const PathArgs A)
+__global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX))
+    k_paths(const PathArgs A)
 {
     using VT = std::conditional_t<SCHEME == HS_SCHEME_QE, double, R>;
     extern __shared__ unsigned char hs_smem[];
@@ -1765,6 +1766,8 @@ hipError_t launch_paths(bool fp32, int nmax, int scheme, int ft, const PathArgs&
     if (a.ck_every > 0 && a.k_begin > 0 &&
         ((a.n - a.k_begin) % a.ck_every != 0 || (a.n - a.k_begin) / a.ck_every < 2))
         return hipErrorInvalidValue;
+    // the block must fit the variant's launch bound
+    if (a.W < 1 || a.W > paths_max_waves(fp32, nmax)) return hipErrorInvalidValue;
     if (!fp32) {
         if (ft != kFeatF64) return hipErrorInvalidValue;
         return scheme == HS_SCHEME_QE

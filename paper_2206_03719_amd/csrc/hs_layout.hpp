@@ -27,6 +27,18 @@ constexpr int paths_tmax_for(bool fp32, bool qe, int nmax)
                  : (nmax <= 8 ? 32 : nmax <= 12 ? 24 : 20);
 }
 
+// Most waves per block of the Greek-set path kernel for a variant.  FP64 at
+// 13-16 assets needs more than 256 registers per lane; at one wave per SIMD
+// (4 waves per block) the compiler holds the excess in the accumulation
+// registers instead of spilling it to memory (16 assets x 25k paths: 104 ->
+// 75 ms of path kernel, 13 assets: 60 -> 41 ms).  At 10 and 12 assets the
+// smaller spill costs less than the halved occupancy, and at 17-20 assets
+// the base assets need 5 waves.
+constexpr int paths_max_waves(bool fp32, int nmax)
+{
+    return (!fp32 && nmax == 16) ? 4 : kMaxWaves;
+}
+
 // Storage type of the path features (U, A) in the workspace.
 enum FeatType { kFeatF32 = 0, kFeatF64 = 1, kFeatF16 = 2, kFeatBF16 = 3 };
 constexpr size_t feat_bytes(int ft) { return ft == kFeatF64 ? 16 : ft == kFeatF32 ? 8 : 4; }

@@ -657,7 +657,7 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
     if (q.opts.waves_per_block == 0 && wmax == 0 && task_groups > kMaxWaves)
         W = wmin <= 4 ? wmin : kMaxWaves;
     W = std::max(W, wmin);
-    W = std::min(W, kMaxWaves);
+    W = std::min(W, paths_max_waves(sh.fp32, sh.nmax));
     pp.W = W;
     pp.nbg = static_cast<int>((gs.size() + W - 1) / W);
     if (sh.fp32)
