@@ -232,6 +232,18 @@ def test_bitwise_invariance_launch_shape_and_passes():
         assert rel(g["scenario_price"], ref["scenario_price"]).max() <= 1e-13
 
 
+def test_bitwise_invariance_fp64_16_asset_wave_cap():
+    # FP64 at 13-16 assets runs at most 4 waves per block: asking for 8, or
+    # fewer, gives the same features and so the same prices bit for bit
+    _say("bitwise invariance: FP64 N=16 waves per block 0, 2, 8")
+    w = W.best_of_call(n_assets=16, n_paths=700, n_steps=12, precision="fp64")
+    ref = gpu(w, "fp64")
+    for wpb in (2, 8):
+        g = gpu(w, "fp64", waves_per_block=wpb)
+        assert np.array_equal(g["scenario_price"], ref["scenario_price"]), wpb
+        assert np.array_equal(g["scenario_se"], ref["scenario_se"]), wpb
+
+
 @pytest.mark.parametrize("P", [16384, 16385, 25000, 70001])
 def test_sweep_variants_vs_oracle(P):
     # cluster sweep (G workgroups per scenario, ragged last workgroup), and the
