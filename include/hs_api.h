@@ -275,8 +275,8 @@ hs_status hs_path_features(const hs_model *model, const double *corr, int64_t n_
  * `repeats` times on hip_stream with the given workspace and stores the
  * fastest in a process-wide table that hs_price_greeks and the server consult
  * when opts.waves_per_block == 0.  These parameters never change results (the
- * backward-sweep shape, which does fix the order of FP64 sums, depends on
- * n_paths alone and is not tuned).  *best_ms (host, may be NULL) receives the
+ * backward-sweep shape, which does fix the order of FP64 sums, depends only
+ * on n_paths, the scenario count and the precision, and is not tuned).  *best_ms (host, may be NULL) receives the
  * winning Greek-set time.  Same arguments and errors as hs_price_greeks. */
 hs_status hs_autotune(const hs_model *model, const double *corr, const hs_option *option,
                       int64_t n_paths, int32_t n_steps, const hs_bumps *bumps,
