@@ -87,7 +87,7 @@ def test_normals(N):
 # paths + path reduction (the paper's measured kernel)
 
 @pytest.mark.parametrize("kernel", ["base", "greek_set"])
-@pytest.mark.parametrize("N", [1, 3, 5, 12, 20])
+@pytest.mark.parametrize("N", [1, 3, 5, 12, 13, 16, 20])
 def test_path_features_fp64(N, kernel):
     _say("path features fp64 N=%d %s kernel" % (N, kernel))
     w = W.best_of_call(n_assets=N, n_paths=1000, n_steps=40)
