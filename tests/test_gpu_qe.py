@@ -57,6 +57,19 @@ def test_qe_path_features_fp64(N, volvol):
     assert np.abs(got[..., 1] - ref[..., 1]).max() <= 1e-15 + 1e-13 * np.abs(ref[..., 1]).max()
 
 
+@pytest.mark.parametrize("N", [5, 16])
+def test_qe_path_features_fp64_greek_set_kernel(N):
+    # the Greek-set path kernel under QE (at 16 assets the variant that runs
+    # at most 4 waves per block)
+    _say("QE path features fp64 N=%d Greek-set kernel" % N)
+    w = high_volvol(W.best_of_call(n_assets=N, n_paths=1000, n_steps=40))
+    ref = oracle.features(w["model"], w["corr"], 1.0, 40, 1000, 42, scheme="qe")
+    got = hs.path_features(w["model"], w["corr"], 1.0, 1000, 40, seed=42, precision="fp64",
+                           scheme="qe", greek_set_kernel=True).cpu().numpy()
+    assert rel(got[..., 0], ref[..., 0]).max() <= 1e-13
+    assert np.abs(got[..., 1] - ref[..., 1]).max() <= 1e-15 + 1e-13 * np.abs(ref[..., 1]).max()
+
+
 @pytest.mark.parametrize("N", [1, 5])
 def test_qe_path_features_fp32(N):
     _say("QE path features fp32 N=%d" % N)
