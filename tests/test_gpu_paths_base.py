@@ -121,7 +121,7 @@ def test_wide_fp32_qe():
 
 @pytest.mark.parametrize("precision,scheme", [("fp64", "euler"), ("fp32", "euler"),
                                               ("fp64", "qe"), ("fp32", "qe")])
-@pytest.mark.parametrize("N", [1, 2, 3, 5, 12, 20])
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 12, 16, 20])
 def test_same_as_greek_set_kernel(N, precision, scheme):
     _say("base vs Greek-set kernel N=%d %s %s" % (N, precision, scheme))
     w = W.best_of_call(n_assets=N, n_paths=333, n_steps=30)
