@@ -60,6 +60,9 @@ def lib(path=None):
                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_uint64, dp]
         L.orc_features_at.restype = ctypes.c_int
+        L.orc_states.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, dp]
+        L.orc_states.restype = ctypes.c_int
         L.orc_lsmc.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                                ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_double, ctypes.c_int32, dp,
@@ -212,6 +215,20 @@ def features_at(model, corr, T, n_steps, paths, seed, scheme="euler"):
                                _dp(out))
     if st != OK:
         raise ValueError("orc_features_at failed with status %d" % st)
+    return out
+
+
+def states(model, corr, T, n_steps, n_paths, seed, nthreads=0, scheme="euler"):
+    """(n_paths, n_assets, 2) array of each asset's (X, v) after n_steps, X
+    from 0 (the per-asset joint law behind the features)."""
+    keep = []
+    m = _model_struct(model, keep, scheme)
+    C = _f64(corr)
+    out = np.empty((n_paths, m.N, 2))
+    st = lib().orc_states(ctypes.byref(m), _dp(C), float(T), int(n_steps), int(n_paths),
+                          int(seed), int(nthreads), _dp(out))
+    if st != OK:
+        raise ValueError("orc_states failed with status %d" % st)
     return out
 
 

@@ -190,9 +190,17 @@ typedef struct {
  *   K2 = gamma2 dt (kappa rho/xi - 1/2) + rho/xi, K3 = gamma1 dt (1 - rho^2),
  *   K4 = gamma2 dt (1 - rho^2)  (rho/xi read as 0 when xi = 0, which the
  *   interface allows only with rho = 0).
- * Random inputs per asset and step (the paper's two numbers per element):
- * Z_x = (L eps)_i, correlated across assets, and Z_v = eta_i, independent;
- * the spot-variance correlation enters through the K coefficients. */
+ * The K2 v' term carries rho times the variance shock, so Z_x is the part of
+ * the spot shock orthogonal to the variance shock.  Random inputs per asset
+ * and step (the paper's two numbers per element), with Z^S = L eps the
+ * correlated spot normals of the Euler scheme:
+ *   Z_v = rho Z^S_i + sqrt(1 - rho^2) eta_i   (the Euler scheme's Z^v),
+ *   Z_x = sqrt(1 - rho^2) Z^S_i - rho eta_i,
+ * independent unit normals whose spot combination rho Z_v + sqrt(1 - rho^2)
+ * Z_x is Z^S_i itself: the spot shocks of different assets keep the
+ * correlation C, and the variance shocks the Euler scheme's rho_i rho_j C_ij,
+ * under both schemes.  For one asset (Z_v, Z_x) is a rotation of (eta, eps),
+ * the same joint law. */
 #define ORC_PSI_C 1.5
 
 typedef struct {
@@ -256,46 +264,59 @@ double orc_qe_variance_step(double kappa, double theta, double xi, double rho, d
  * in log price:
  *   v+ = max(v, 0);  X += (r - v+/2) dt + sqrt(v+ dt) Z^S;
  *   v += kappa (theta - v+) dt + xi sqrt(v+ dt) Z^v;  S = S0 exp(X), X_0 = 0.
- * Scheme ORC_QE: the quadratic-exponential step above, with Z_x = Z^S and
- * Z_v = eta (v stays >= 0, so max(v, 0) = v).
+ * Scheme ORC_QE: the quadratic-exponential step above, with Z_v and Z_x
+ * formed from Z^S and eta as stated there (v stays >= 0, so max(v, 0) = v).
  * Reduction at each date k = 1..n (Sec. 4.1): U = max_i S_i (U = S for one
  * asset) and A = (1/N) sum_i max(v_i, 0).
  * Output feat[((k-1) P + p) * 2 + {0,1}] = (U, A). */
 /* One path p: n steps from X = 0, v = v0; writes (U, A) of date k = 1..n to
  * out[(k-1) stride * 2 + {0,1}].  work holds 5 N doubles. */
+/* Step k (date k to k + 1) of every asset of path p: (X, v) in place.  work
+ * holds 3 N doubles. */
+static void step(const orc_model *m, const double *L, double dt, int32_t k, int64_t p,
+                 uint64_t seed, double *X, double *v, double *work)
+{
+    const int N = m->N;
+    double *eps = work, *eta = work + N, *ZS = work + 2 * N;
+    orc_normals(N, seed, p, k, eps, eta);
+    for (int a = 0; a < N; ++a) {
+        double z = 0.0;
+        for (int b = 0; b <= a; ++b) z += L[a * N + b] * eps[b];
+        ZS[a] = z;
+    }
+    if (m->scheme == ORC_QE) {
+        for (int a = 0; a < N; ++a) {
+            qe_consts q;
+            qe_consts_for(m->kappa[a], m->theta[a], m->xi[a], m->rho[a], m->r, dt, &q);
+            const double rho = m->rho[a], rhobar = sqrt(1.0 - rho * rho);
+            const double Zv = rho * ZS[a] + rhobar * eta[a];
+            const double Zx = rhobar * ZS[a] - rho * eta[a];
+            const double vn = qe_variance(&q, v[a], Zv);
+            X[a] = X[a] + q.K0 + q.K1 * v[a] + q.K2 * vn + sqrt(q.K3 * v[a] + q.K4 * vn) * Zx;
+            v[a] = vn;
+        }
+    } else
+    for (int a = 0; a < N; ++a) {
+        double rho = m->rho[a];
+        double Zv = rho * ZS[a] + sqrt(1.0 - rho * rho) * eta[a];
+        double vp = v[a] > 0.0 ? v[a] : 0.0;
+        double sq = sqrt(vp * dt);
+        X[a] = X[a] + (m->r - 0.5 * vp) * dt + sq * ZS[a];
+        v[a] = v[a] + m->kappa[a] * (m->theta[a] - vp) * dt + m->xi[a] * sq * Zv;
+    }
+}
+
 static void one_path(const orc_model *m, const double *L, double dt, int32_t n, int64_t p,
                      uint64_t seed, double *work, double *out, int64_t stride)
 {
     const int N = m->N;
-    double *X = work, *v = work + N, *eps = work + 2 * N, *eta = work + 3 * N, *ZS = work + 4 * N;
+    double *X = work, *v = work + N;
     for (int a = 0; a < N; ++a) {
         X[a] = 0.0;
         v[a] = m->v0[a];
     }
     for (int32_t k = 0; k < n; ++k) {
-        orc_normals(N, seed, p, k, eps, eta);
-        for (int a = 0; a < N; ++a) {
-            double z = 0.0;
-            for (int b = 0; b <= a; ++b) z += L[a * N + b] * eps[b];
-            ZS[a] = z;
-        }
-        if (m->scheme == ORC_QE) {
-            for (int a = 0; a < N; ++a) {
-                qe_consts q;
-                qe_consts_for(m->kappa[a], m->theta[a], m->xi[a], m->rho[a], m->r, dt, &q);
-                const double vn = qe_variance(&q, v[a], eta[a]);
-                X[a] = X[a] + q.K0 + q.K1 * v[a] + q.K2 * vn + sqrt(q.K3 * v[a] + q.K4 * vn) * ZS[a];
-                v[a] = vn;
-            }
-        } else
-        for (int a = 0; a < N; ++a) {
-            double rho = m->rho[a];
-            double Zv = rho * ZS[a] + sqrt(1.0 - rho * rho) * eta[a];
-            double vp = v[a] > 0.0 ? v[a] : 0.0;
-            double sq = sqrt(vp * dt);
-            X[a] = X[a] + (m->r - 0.5 * vp) * dt + sq * ZS[a];
-            v[a] = v[a] + m->kappa[a] * (m->theta[a] - vp) * dt + m->xi[a] * sq * Zv;
-        }
+        step(m, L, dt, k, p, seed, X, v, work + 2 * N);
         double U = -INFINITY, sv = 0.0;
         for (int a = 0; a < N; ++a) {
             double S = m->S0[a] * exp(X[a]);
@@ -366,6 +387,53 @@ int orc_features_at(const orc_model *m, const double *C, double T, int32_t n, in
     free(L);
     free(work);
     return st;
+}
+
+/* Per-asset state after n steps of every path p < P (test access: the joint
+ * law of the assets' log prices and variances):
+ * out[(p N + a) * 2 + {0,1}] = (X_{a,n}, v_{a,n}), X from 0. */
+int orc_states(const orc_model *m, const double *C, double T, int32_t n, int64_t P,
+               uint64_t seed, int32_t nthreads, double *out)
+{
+    const int N = m->N;
+    if (N < 1 || n < 1 || P < 1 || !(T > 0.0)) return ORC_EINVAL;
+    double *L = (double *)malloc(sizeof(double) * N * N);
+    if (!L) return ORC_ENOMEM;
+    int st = orc_cholesky(N, C, L);
+    if (st != ORC_OK) {
+        free(L);
+        return st;
+    }
+    const double dt = T / (double)n;
+    const int64_t nchunk = (P + ORC_CHUNK - 1) / ORC_CHUNK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * N * 5);
+#pragma omp for schedule(static)
+        for (int64_t c = 0; c < nchunk; ++c) {
+            int64_t pend = (c + 1) * ORC_CHUNK < P ? (c + 1) * ORC_CHUNK : P;
+            for (int64_t p = c * ORC_CHUNK; p < pend; ++p) {
+                double *X = work, *v = work + N;
+                for (int a = 0; a < N; ++a) {
+                    X[a] = 0.0;
+                    v[a] = m->v0[a];
+                }
+                for (int32_t k = 0; k < n; ++k) step(m, L, dt, k, p, seed, X, v, work + 2 * N);
+                for (int a = 0; a < N; ++a) {
+                    out[(p * N + a) * 2] = X[a];
+                    out[(p * N + a) * 2 + 1] = v[a];
+                }
+            }
+        }
+        free(work);
+    }
+    free(L);
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -117,6 +117,13 @@ MUTANTS = [
     ("qe-kappa-term-in-K2-dropped", "q->K2 = g2 * dt * (kappa * rx - 0.5) + rx;",
      "q->K2 = g2 * dt * (-0.5) + rx;",
      [lambda: TQ.test_heston_semi_closed_form(0.04, 1.0, 0.04, 1.0, -0.5, (70.0, 100.0, 130.0))]),
+    ("qe-independent-variance-shocks",
+     "const double Zv = rho * ZS[a] + rhobar * eta[a];\n            const double Zx = rhobar * ZS[a] - rho * eta[a];",
+     "const double Zv = eta[a];\n            const double Zx = ZS[a];",
+     [lambda: TQ.test_joint_law_of_one_step("qe")]),
+    ("qe-orthogonal-part-sign", "const double Zx = rhobar * ZS[a] - rho * eta[a];",
+     "const double Zx = rhobar * ZS[a] + rho * eta[a];",
+     [lambda: TQ.test_joint_law_of_one_step("qe")]),
     ("qe-uniform-from-wrong-tail", "const double u = 0.5 * erfc(-zv / sqrt(2.0));",
      "const double u = 0.5 * erfc(zv / sqrt(2.0));",
      [lambda: TQ.test_variance_step_matches_cir_moments(0.0005), TQ.test_variance_step_branches]),

@@ -143,3 +143,60 @@ def test_heston_semi_closed_form(v0, kappa, theta, xi, rho, strikes):
     assert abs(mean - 100.0) < 4 * se + 2 * abs(disc * (f32[-1, :, 0].mean() - ST.mean()))
     # QE variance never goes negative
     assert f64[:, :, 1].min() >= 0.0
+
+
+def _three_assets():
+    beta = np.array([0.75, 0.6, 0.5])
+    C = np.outer(beta, beta)
+    np.fill_diagonal(C, 1.0)
+    m = _model([100.0, 95.0, 110.0], [0.04, 0.06, 0.05], [2.0, 1.5, 3.0], [0.04, 0.06, 0.05],
+               [0.5, 0.4, 0.3], [-0.7, -0.5, -0.3], 0.02)
+    return m, C
+
+
+@pytest.mark.parametrize("scheme", ["euler", "qe"])
+def test_joint_law_of_one_step(scheme):
+    """One daily step from fixed (X, v) = (0, v0): the assets' log-price shocks
+    correlate as C_ij, the variance shocks as rho_i rho_j C_ij, and the spot of
+    asset i with the variance of asset j as rho_j C_ij (the continuous model's
+    instantaneous correlations).  Bar: 4 standard errors of a sample
+    correlation, (1 - c^2)/sqrt(P), plus 0.003 for the step's own departure
+    from the instantaneous law (measured well below that: halving dt twice
+    moves the estimates by < 5e-4)."""
+    m, C = _three_assets()
+    rho = m["rho"]
+    P = 200000
+    st = oracle.states(m, C, 1.0 / 252, 1, P, 11, scheme=scheme)
+    Z = np.concatenate([st[:, :, 0], st[:, :, 1]], axis=1)  # X_0..2, v_0..2
+    c = np.corrcoef(Z.T)
+    N = 3
+    for i in range(N):
+        for j in range(N):
+            vv = 1.0 if i == j else rho[i] * rho[j] * C[i, j]
+            want = {"XX": C[i, j], "vv": vv, "Xv": rho[j] * C[i, j]}
+            got = {"XX": c[i, j], "vv": c[N + i, N + j], "Xv": c[i, N + j]}
+            for k in want:
+                bar = 4 * (1 - want[k] ** 2) / math.sqrt(P) + 0.003
+                assert abs(got[k] - want[k]) <= bar, (scheme, k, i, j, got[k], want[k])
+
+
+@pytest.mark.slow
+def test_multi_asset_qe_matches_euler_european():
+    """Under the same joint law both schemes converge to one price as dt -> 0:
+    a 5-asset European best-of call (the workload's draws) under QE and
+    full-truncation Euler agree within 4 standard errors of their pathwise
+    difference plus twice each scheme's time-step bias, estimated by halving
+    dt."""
+    import workloads as W
+    w = W.best_of_call(5, 200000, 64)
+    mod, C, K, T, r = w["model"], w["corr"], w["option"]["K"], 1.0, w["model"]["r"]
+    P = 200000
+    pay = {}
+    for scheme in ("euler", "qe"):
+        for n in (32, 64):
+            f = oracle.features(mod, C, T, n, P, 5, scheme=scheme)
+            pay[scheme, n] = math.exp(-r * T) * np.maximum(f[-1, :, 0] - K, 0.0)
+    d = pay["qe", 64] - pay["euler", 64]
+    se = d.std(ddof=1) / math.sqrt(P)
+    bias = sum(abs(pay[s, 64].mean() - pay[s, 32].mean()) for s in ("euler", "qe"))
+    assert abs(d.mean()) <= 4 * se + 2 * bias, (d.mean(), se, bias)
