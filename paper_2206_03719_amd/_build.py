@@ -22,7 +22,16 @@ HIP_FLAGS = ["-std=c++17", "-O3", "--offload-arch=" + ARCH, "-fPIC", "-ffp-contr
              "-Wall", "-Wno-unused-function"]
 HOST_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-ffp-contract=off", "-Wall"]
 
+# the path-kernel variants are split over several sources so that they
+# compile in parallel
 SOURCES = [
+    ("hs_paths_f32e.hip", HIP_FLAGS),
+    ("hs_paths_f64e.hip", HIP_FLAGS),
+    ("hs_paths_f32q.hip", HIP_FLAGS),
+    ("hs_paths_f64q.hip", HIP_FLAGS),
+    ("hs_paths_f32h.hip", HIP_FLAGS),
+    ("hs_lsmc.hip", HIP_FLAGS),
+    ("hs_paths_base.hip", HIP_FLAGS),
     ("hs_kernels.hip", HIP_FLAGS),
     ("hs_plan.cpp", HOST_FLAGS),
     ("hs_api.cpp", HOST_FLAGS),
@@ -47,7 +56,7 @@ def _compile(src, flags, verbose):
 
 def build(verbose=False):
     os.makedirs(OUT_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 8)) as ex:
         futs = [ex.submit(_compile, s, f, verbose) for s, f in SOURCES]
         objs = [f.result() for f in futs]
     tmp = LIB + ".tmp%d" % os.getpid()

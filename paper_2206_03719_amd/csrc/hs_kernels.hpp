@@ -13,15 +13,23 @@ namespace hs {
 // tasks per wave for a bucket, and the dynamic LDS it needs.
 int paths_nmax_bucket(int N);
 int paths_tmax(bool fp32, int scheme, int nmax);
-size_t paths_lds_bytes(bool fp32, int nmax);
+size_t paths_lds_bytes(bool fp32, int scheme, int nmax);
 hipError_t launch_paths(bool fp32, int nmax, int scheme, int feat, const PathArgs& a, int nchunks,
                         int nblockgroups, hipStream_t st);
+// The variants behind launch_paths, one source each: FP32 Euler with FP32
+// features (f32e) or 16-bit features (f32h), FP32 QE (f32q), FP64 Euler
+// (f64e) and FP64 QE (f64q).
+hipError_t launch_paths_f32e(int nmax, int ft, const PathArgs& a, int nchunks, int nbg, hipStream_t st);
+hipError_t launch_paths_f32h(int nmax, int ft, const PathArgs& a, int nchunks, int nbg, hipStream_t st);
+hipError_t launch_paths_f32q(int nmax, int ft, const PathArgs& a, int nchunks, int nbg, hipStream_t st);
+hipError_t launch_paths_f64e(int nmax, int ft, const PathArgs& a, int nchunks, int nbg, hipStream_t st);
+hipError_t launch_paths_f64q(int nmax, int ft, const PathArgs& a, int nchunks, int nbg, hipStream_t st);
 
 // Base-scenario path kernel (features of the model alone): Philox blocks per
 // wave for N assets and W waves (1, 2 or 4; -1 if this W does not fit), its
 // dynamic LDS, and the launch over ceil(P / 64) blocks of W waves.
 int paths_base_bpw(bool fp32, int scheme, int N, int W);
-size_t paths_base_lds_bytes(bool fp32, int N, int W);
+size_t paths_base_lds_bytes(bool fp32, int scheme, int N, int W);
 hipError_t launch_paths_base(bool fp32, int scheme, int feat, const BasePathArgs& a,
                              hipStream_t st);
 

@@ -45,13 +45,15 @@ constexpr size_t feat_bytes(int ft) { return ft == kFeatF64 ? 16 : ft == kFeatF3
 
 // Quadratic-exponential step constants of one asset of one scenario (host
 // FP64): E = exp(-kappa dt), mth = theta (1 - E), c1, c2 with the CIR
-// conditional variance s^2 = v c1 + c2, the initial variance v0, and the
-// log-price coefficients K0 (with r dt), K1..K4.  All FP64: the variance path
-// and the log-price drift run in FP64 in both path precisions (K1 and K2 are
-// near -rho/xi and +rho/xi, and their FP32 roundings would not cancel).
+// conditional variance s^2 = v c1 + c2, the initial variance v0, the
+// log-price coefficients K0 (with r dt), K1..K4, and rho, sqrt(1 - rho^2)
+// that split the spot normal into the variance normal and its orthogonal
+// part.  All FP64: the variance path and the log-price drift run in FP64 in
+// both path precisions (K1 and K2 are near -rho/xi and +rho/xi, and their
+// FP32 roundings would not cancel).
 template <typename R>
 struct QeP {
-    double E, mth, c1, c2, v0, K0, K1, K2, K3, K4;
+    double E, mth, c1, c2, v0, K0, K1, K2, K3, K4, rho, rhobar;
 };
 
 // One asset of the base scenario.  rhobar = sqrt(1 - rho^2) (host FP64).
@@ -66,6 +68,7 @@ template <typename R>
 struct BaseP {
     AssetP<R> a[kMaxAssets];
     R L[kMaxAssets * kMaxAssets];  // chol(C), row-major, upper part zero
+    double L64[kMaxAssets * kMaxAssets];  // the same in FP64 (QE: FP64 spot normals)
     R S0_up[kMaxAssets];           // S0_i (1 + h) for the spot-up scenarios
     R S0_dn[kMaxAssets];           // S0_i (1 - h)
     R r, dt, invN, pad;
@@ -80,6 +83,7 @@ struct TaskP {
     int32_t asset, own_row, first, last, scen, lo, hi, pad;
     R S0, v0, kappa, theta, xi, rho, rhobar, r, dt, pad1;
     R L[kMaxAssets];  // the scenario's Cholesky row of `asset` (own_row == 1)
+    double L64[kMaxAssets];  // the same in FP64 (QE)
     QeP<R> qe;
 };
 
@@ -114,10 +118,12 @@ template <typename R>
 struct ModelP {
     AssetP<R> a[kMaxPathAssets];
     R L[(kMaxPathAssets + 2) * kMaxPathAssets];
+    double L64[(kMaxPathAssets + 2) * kMaxPathAssets];  // the same in FP64 (QE)
     R r, dt, invN, pad;
 };
 // Philox blocks per correlation chunk of the base-model kernel (the eps
-// buffer in LDS is padded with zeros to a whole number of chunks).
+// buffer in LDS is padded with zeros to a whole number of chunks); fp32: the
+// spot normals are FP32 (FP32 Euler paths; under QE they are FP64).
 constexpr int base_chunk(bool fp32) { return fp32 ? 4 : 2; }
 
 struct BasePathArgs {

@@ -472,7 +472,8 @@ namespace {
 // E = e^{-kappa dt}; m = mth + v E and s^2 = v c1 + c2 are the CIR conditional
 // mean and variance; K0 (with r dt) .. K4 the central (gamma = 1/2) log-price
 // coefficients, with rho/xi read as 0 when xi = 0 (validation then demands
-// rho = 0).
+// rho = 0); rho and sqrt(1 - rho^2) split the asset's spot normal into the
+// variance normal and the log price's orthogonal normal.
 template <typename R>
 QeP<R> qe_params(double v0, double kappa, double theta, double xi, double rho, double r, double dt)
 {
@@ -491,6 +492,8 @@ QeP<R> qe_params(double v0, double kappa, double theta, double xi, double rho, d
     c.K2 = 0.5 * dt * (kappa * rx - 0.5) + rx;
     c.K3 = 0.5 * dt * (1.0 - rho * rho);
     c.K4 = 0.5 * dt * (1.0 - rho * rho);
+    c.rho = rho;
+    c.rhobar = std::sqrt(1.0 - rho * rho);
     return c;
 }
 
@@ -511,7 +514,10 @@ std::vector<unsigned char> model_table_t(const Request& q, const Scenario& b0)
         mp.a[a].rho = static_cast<R>(q.rho[a]);
         mp.a[a].rhobar = static_cast<R>(std::sqrt(1.0 - q.rho[a] * q.rho[a]));
         mp.a[a].qe = qe_params<R>(q.v0[a], q.kappa[a], q.theta[a], q.xi[a], q.rho[a], q.r, dt);
-        for (int c = 0; c <= a; ++c) mp.L[a * kMaxPathAssets + c] = static_cast<R>(b0.L[a * N + c]);
+        for (int c = 0; c <= a; ++c) {
+            mp.L[a * kMaxPathAssets + c] = static_cast<R>(b0.L[a * N + c]);
+            mp.L64[a * kMaxPathAssets + c] = b0.L[a * N + c];
+        }
     }
     mp.r = static_cast<R>(q.r);
     mp.dt = static_cast<R>(dt);
@@ -539,7 +545,10 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
         bp.a[a].rhobar = static_cast<R>(std::sqrt(1.0 - q.rho[a] * q.rho[a]));
         bp.a[a].qe = qe_params<R>(q.v0[a], q.kappa[a], q.theta[a], q.xi[a], q.rho[a], q.r,
                                   q.opt.T / static_cast<double>(q.n));
-        for (int c = 0; c < N; ++c) bp.L[a * kMaxAssets + c] = static_cast<R>(b0.L[a * N + c]);
+        for (int c = 0; c < N; ++c) {
+            bp.L[a * kMaxAssets + c] = static_cast<R>(b0.L[a * N + c]);
+            bp.L64[a * kMaxAssets + c] = b0.L[a * N + c];
+        }
         bp.S0_up[a] = static_cast<R>(q.S0[a] * (1.0 + q.bumps.spot_rel));
         bp.S0_dn[a] = static_cast<R>(q.S0[a] * (1.0 - q.bumps.spot_rel));
     }
@@ -590,7 +599,10 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
                 t.dt = static_cast<R>(s.T / static_cast<double>(q.n));
                 t.qe = qe_params<R>(s.v0[a], q.kappa[a], q.theta[a], q.xi[a], q.rho[a], s.r,
                                     s.T / static_cast<double>(q.n));
-                for (int c = 0; c < N; ++c) t.L[c] = static_cast<R>(s.L[a * N + c]);
+                for (int c = 0; c < N; ++c) {
+                    t.L[c] = static_cast<R>(s.L[a * N + c]);
+                    t.L64[c] = s.L[a * N + c];
+                }
                 tasks.push_back(t);
             }
         }
