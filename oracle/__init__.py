@@ -83,6 +83,10 @@ def lib(path=None):
                                                  ctypes.POINTER(ctypes.c_int32),
                                                  ctypes.POINTER(ctypes.c_int32)]
         L.orc_price_scenarios_replay.restype = ctypes.c_int
+        L.orc_price_scenarios_dcf.argtypes = [ctypes.c_void_p, dp, dp,
+                                              ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_int32), dp]
+        L.orc_price_scenarios_dcf.restype = ctypes.c_int
         L.orc_greeks.argtypes = [ctypes.c_int32, ctypes.c_uint32, dp, dp, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, dp, dp, dp, dp, dp, dp, dp]
@@ -281,11 +285,12 @@ def qe_variance_step(kappa, theta, xi, rho, dt, v, zv):
 
 
 def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed, nthreads=0,
-                 export_tau=False, replay_tau=None, scheme="euler"):
+                 export_tau=False, replay_tau=None, scheme="euler", export_dcf=False):
     """The full Greek set: scenario prices, SEs, skipped counts and the Greeks.
 
     replay_tau (scenarios x paths int32): price each scenario with these
-    exercise dates instead of regressing (decision replay)."""
+    exercise dates instead of regressing (decision replay).  export_dcf: also
+    return "dcf" (scenarios x paths), each path's discounted cash flow."""
     keep = []
     arrs = [_f64(model[k]) for k in ("S0", "v0", "kappa", "theta", "xi", "rho")]
     C = _f64(corr)
@@ -308,11 +313,19 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed, nthreads=0,
     if replay_tau is not None:
         rt = np.ascontiguousarray(replay_tau, dtype=np.int32)
         assert rt.shape == (S, n_paths)
-    st = lib().orc_price_scenarios_replay(
-        ctypes.byref(q), _dp(prices), _dp(ses),
-        skipped.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-        tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if tau is not None else None,
-        rt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if rt is not None else None)
+    taup = tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if tau is not None else None
+    dcf = None
+    if export_dcf:
+        assert rt is None
+        dcf = np.zeros((S, n_paths))
+        st = lib().orc_price_scenarios_dcf(
+            ctypes.byref(q), _dp(prices), _dp(ses),
+            skipped.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), taup, _dp(dcf))
+    else:
+        st = lib().orc_price_scenarios_replay(
+            ctypes.byref(q), _dp(prices), _dp(ses),
+            skipped.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), taup,
+            rt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if rt is not None else None)
     if st != OK:
         raise ValueError("orc_price_scenarios failed with status %d" % st)
     g = greeks_from_prices(N, mask, arrs[0], arrs[1], bumps, prices)
@@ -320,6 +333,8 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed, nthreads=0,
               "price": prices[0], "price_se": ses[0], "n_scenarios": S})
     if tau is not None:
         g["tau"] = tau
+    if dcf is not None:
+        g["dcf"] = dcf
     return g
 
 

@@ -706,17 +706,33 @@ typedef struct {
  * orc_num_scenarios entries; tau_all (optional) has that many rows of P.
  * With replay_tau (optional, same shape) each scenario is not regressed but
  * priced with the given exercise dates (decision replay). */
-int orc_price_scenarios_replay(const orc_request *q, double *prices, double *ses,
-                               int64_t *skipped, int32_t *tau_all, const int32_t *replay_tau);
+static int price_scenarios(const orc_request *q, double *prices, double *ses, int64_t *skipped,
+                           int32_t *tau_all, const int32_t *replay_tau, double *dcf_all);
 
 int orc_price_scenarios(const orc_request *q, double *prices, double *ses, int64_t *skipped,
                         int32_t *tau_all)
 {
-    return orc_price_scenarios_replay(q, prices, ses, skipped, tau_all, NULL);
+    return price_scenarios(q, prices, ses, skipped, tau_all, NULL, NULL);
 }
 
 int orc_price_scenarios_replay(const orc_request *q, double *prices, double *ses,
                                int64_t *skipped, int32_t *tau_all, const int32_t *replay_tau)
+{
+    return price_scenarios(q, prices, ses, skipped, tau_all, replay_tau, NULL);
+}
+
+/* The same, also returning each path's discounted cash flow CF_p exp(-r tau_p
+ * dt) per scenario in dcf_all [S][P] (the terms whose mean is the price; the
+ * tests take the Monte Carlo standard error of a finite-difference Greek over
+ * the paths from it). */
+int orc_price_scenarios_dcf(const orc_request *q, double *prices, double *ses, int64_t *skipped,
+                            int32_t *tau_all, double *dcf_all)
+{
+    return price_scenarios(q, prices, ses, skipped, tau_all, NULL, dcf_all);
+}
+
+static int price_scenarios(const orc_request *q, double *prices, double *ses, int64_t *skipped,
+                           int32_t *tau_all, const int32_t *replay_tau, double *dcf_all)
 {
     const int N = q->N;
     if (N < 1 || q->P < 2 || q->n < 1) return ORC_EINVAL;
@@ -778,6 +794,16 @@ int orc_price_scenarios_replay(const orc_request *q, double *prices, double *ses
         int64_t sk = 0;
         if (replay_tau) {
             st = orc_replay(feat, q->P, q->n, T, r, q->K, q->cp, replay_tau + s * q->P, out);
+        } else if (dcf_all) {
+            int32_t *tau = (int32_t *)malloc(sizeof(int32_t) * q->P);
+            double *cf = dcf_all + s * q->P;
+            if (!tau) { st = ORC_ENOMEM; break; }
+            st = orc_lsmc(feat, q->P, q->n, T, r, q->K, q->cp, q->style, q->m, tbar, q->nthreads,
+                          out, tau, cf, &sk);
+            const double dt = T / (double)q->n;
+            for (int64_t p = 0; p < q->P; ++p) cf[p] = cf[p] * exp(-r * (double)tau[p] * dt);
+            if (tau_all) memcpy(tau_all + s * q->P, tau, sizeof(int32_t) * q->P);
+            free(tau);
         } else {
             st = orc_lsmc(feat, q->P, q->n, T, r, q->K, q->cp, q->style, q->m, tbar, q->nthreads,
                           out, tau_all ? tau_all + s * q->P : NULL, NULL, &sk);

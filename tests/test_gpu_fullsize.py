@@ -6,7 +6,8 @@ largest runs.
 
 - 10 assets, 200k paths x 252 steps, the full 78-scenario Greek set in the
   benchmark's launch configuration (graph replay, autotuned): FP32 scenario
-  prices <= 1e-4 and delta/gamma of asset 0 <= 1e-3 relative to the oracle;
+  prices <= 1e-4, and delta, gamma and vega of assets 0 and 9, theta, rho and
+  three correlation Greeks within the FP32 Greek bar (tests/_greekbar.py);
   FP64 base scenario identical exercise dates and <= 1e-12.
 - 10 assets, 100k paths: FP32 and FP64 Greek sets side by side against the
   oracle on the same Philox streams (report written to gpurun_out/).
@@ -21,6 +22,7 @@ import sys
 import numpy as np
 import pytest
 
+import _greekbar as GB
 import oracle
 import workloads as W
 
@@ -76,10 +78,10 @@ def bumped(w, s):
     return m, C, opt
 
 
-def oracle_scenario(w, s, export_tau=False):
+def oracle_scenario(w, s, export_tau=False, export_dcf=False):
     m, C, opt = bumped(w, s)
     o = oracle.price_greeks(m, C, opt, w["n_paths"], w["n_steps"], dict(w["bumps"], mask=0),
-                            w["seed"], export_tau=export_tau)
+                            w["seed"], export_tau=export_tau, export_dcf=export_dcf)
     return o
 
 
@@ -105,23 +107,30 @@ def test_ten_assets_200k_greek_set():
     del ws
     torch.cuda.empty_cache()
     assert g["n_scenarios"] == 78
-    # base, spot up/down of assets 0 and 9, v0 of asset 4, T, r, corr (0,1), (4,5), (8,9)
-    pick = [0, 1, 1 + N, 10, 20, 25, 31, 32, 33, 33 + 30, 77]
-    errs = {}
-    o = {}
+    # every scenario behind the asserted Greeks: delta, gamma and vega of
+    # assets 0 and 9, theta, rho, and the correlation Greeks of the pairs
+    # (0, 1), (4, 5) and (8, 9)
+    st = GB.stencils(N, w["bumps"]["mask"], w["model"]["S0"], w["model"]["v0"], w["bumps"])
+    names = ["delta_0", "gamma_0", "vega_0", "delta_9", "gamma_9", "vega_9", "theta", "rho",
+             "corr_0_1", "corr_4_5", "corr_8_9"]
+    pick = sorted({s for nm in names for s, _ in st[nm][0]})
+    errs, price, dcf = {}, {}, {}
     for s in pick:
-        o[s] = oracle_scenario(w, s)["price"]
-        errs[s] = rel(g["scenario_price"][s], o[s])
-    h = w["bumps"]["spot_rel"] * w["model"]["S0"][0]
-    d_or = (o[1] - o[1 + N]) / (2 * h)
-    g_or = (o[1] - 2 * o[0] + o[1 + N]) / h ** 2
-    rep = {"max_price_rel_err": max(errs.values()),
-           "delta0_rel_err": rel(g["delta"][0], d_or), "gamma0_rel_err": rel(g["gamma"][0], g_or),
-           "scenarios_checked": pick}
+        _say("  oracle scenario %d" % s)
+        os_ = oracle_scenario(w, s, export_dcf=True)
+        price[s], dcf[s] = os_["price"], os_["dcf"][0]
+        errs[s] = rel(g["scenario_price"][s], price[s])
+    greeks = {}
+    for nm in names:
+        terms, unit = st[nm]
+        oval = sum(c * price[s] for s, c in terms)
+        greeks[nm] = GB.compare(GB.greek_value(g, nm), oval, terms, unit, price[0], dcf)
+    rep = {"max_price_rel_err": max(errs.values()), "scenarios_checked": pick,
+           "max_greek_rel_err": max(v["rel_err"] for v in greeks.values()), "greeks": greeks}
     report("10x200000x252_fp32", rep)
     assert rep["max_price_rel_err"] <= 1e-4
-    assert rep["delta0_rel_err"] <= 1e-3
-    assert rep["gamma0_rel_err"] <= 1e-3
+    bad = {k: v["rel_err"] for k, v in greeks.items() if v["rel_err"] > GB.BAR}
+    assert not bad, bad
 
 
 def test_ten_assets_200k_fp64_base_identical_decisions():

@@ -3,8 +3,9 @@ the same seeded inputs and the same Philox streams.
 
 Bars: bit-exact Philox words; FP64 paths within 1e-13 relative of the oracle's
 features and every FP64 scenario price within 1e-12 relative with identical
-exercise dates; FP32 paths within 1e-4 relative on prices and 1e-3 on deltas,
-with the decision flips counted (and, as a reported diagnostic only, the FP64
+exercise dates; FP32 paths within 1e-4 relative on prices and 1e-3 on every
+Greek (relative to max(|ref|, rounding floor, the Greek's own Monte Carlo
+error), tests/_greekbar.py), with the decision flips counted (and, as a reported diagnostic only, the FP64
 reprice of the GPU's own exercise dates); bit-for-bit invariance across launch
 shapes, sweep modes and workspace passes."""
 import json
@@ -15,6 +16,7 @@ import sys
 import numpy as np
 import pytest
 
+import _greekbar as GB
 import oracle
 import workloads as W
 
@@ -171,29 +173,38 @@ def test_put_on_max_fp64():
 # ---------------------------------------------------------------------------
 # Greek sets, FP32 paths (FP64 regression): 1e-4 on prices, decisions replayed
 
-def _fp32_parity(w):
-    g = gpu(w, "fp32", export_tau=True)
-    o = orc(w, export_tau=True)
-    rep = orc(w, replay_tau=g["tau"])  # FP64 prices of the GPU's own decisions
+def _fp32_parity(w, scheme="euler"):
+    g = gpu(w, "fp32", export_tau=True, scheme=scheme)
+    o = orc(w, export_tau=True, export_dcf=True, scheme=scheme)
+    rep = orc(w, replay_tau=g["tau"], scheme=scheme)  # FP64 prices of the GPU's own decisions
     price_err = rel(g["scenario_price"], o["scenario_price"])
     arith_err = rel(g["scenario_price"], rep["scenario_price"])
     flips = (g["tau"] != o["tau"]).sum(axis=1)
-    report = {"workload": w["name"], "max_price_rel_err": float(price_err.max()),
+    report = {"workload": w["name"], "scheme": scheme, "max_price_rel_err": float(price_err.max()),
               "max_arith_rel_err": float(arith_err.max()),
               "flip_fraction": float(flips.sum() / g["tau"].size)}
-    for key in ("delta", "gamma", "vega", "corr"):
-        if len(o[key]):
-            report["max_%s_rel_err" % key] = float(rel(g[key], o[key]).max())
-    for key in ("theta", "rho"):
-        report["%s_rel_err" % key] = float(rel(g[key], o[key]))
-    _say("  fp32 " + json.dumps(report))
+    # every Greek against the FP32 Greek bar (tests/_greekbar.py: relative to
+    # max(|ref|, rounding floor, its own Monte Carlo standard error))
+    N = len(w["model"]["S0"])
+    st = GB.stencils(N, w["bumps"]["mask"], w["model"]["S0"], w["model"]["v0"], w["bumps"])
+    GB.check_stencils(o, st)
+    greeks = {name: GB.compare(GB.greek_value(g, name), GB.greek_value(o, name), terms, unit,
+                               o["price"], o["dcf"])
+              for name, (terms, unit) in st.items()}
+    worst = max(greeks, key=lambda k: greeks[k]["rel_err"])
+    report["max_greek_rel_err"] = greeks[worst]["rel_err"]
+    report["worst_greek"] = worst
+    report["noise_level_greeks"] = [k for k, v in greeks.items() if v["noise_level"]]
+    report["greeks"] = greeks
+    _say("  fp32 " + json.dumps({k: v for k, v in report.items() if k != "greeks"}))
     os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "fp32_parity_%s.json" % w["name"]), "w") as f:
+    with open(os.path.join("gpurun_out", "fp32_parity_%s_%s.json" % (w["name"], scheme)), "w") as f:
         json.dump(report, f, indent=1)
     # the replay figure uses the GPU's exercise dates as oracle input: a
     # diagnostic in the report, not a parity assertion
     assert price_err.max() <= 1e-4
-    assert rel(g["delta"], o["delta"]).max() <= 1e-3
+    bad = {k: v["rel_err"] for k, v in greeks.items() if v["rel_err"] > GB.BAR}
+    assert not bad, bad
     return g, o, report
 
 

@@ -6,7 +6,9 @@ identical exercise dates.  FP32: the branch test runs in FP64 on the FP32
 state, which differs from the oracle's FP64 state by rounding, so a path whose
 psi passes within rounding of 1.5 may take the other branch from there on;
 features are checked on all but a tiny fraction of paths, and prices within
-1e-4 at the full 5-asset 25k x 252 size."""
+1e-4 and every Greek within the FP32 Greek bar at the full 5-asset 25k x 252
+size.  Several assets: QE and Euler price the same joint law (a European
+best-of call agrees within the time-step bias)."""
 import sys
 
 import numpy as np
@@ -101,13 +103,29 @@ def test_qe_greek_set_fp64(N, P, n, volvol):
 
 
 def test_qe_greek_set_fp32_full_size():
+    # prices within 1e-4 and every Greek within the FP32 Greek bar
     _say("QE greek set fp32 N=5 P=25000 n=252 (full size)")
-    w = W.best_of_call(n_assets=5, n_paths=25000, n_steps=252)
-    g = hs.price_greeks(w["model"], w["corr"], w["option"], 25000, 252, w["bumps"],
-                        seed=w["seed"], precision="fp32", scheme="qe")
-    o = oracle.price_greeks(w["model"], w["corr"], w["option"], 25000, 252, w["bumps"],
-                            w["seed"], scheme="qe")
-    err = rel(g["scenario_price"], o["scenario_price"])
-    _say("  max price rel err %.3e, delta %.3e" % (err.max(), rel(g["delta"], o["delta"]).max()))
-    assert err.max() <= 1e-4
-    assert rel(g["delta"], o["delta"]).max() <= 1e-3
+    import test_gpu_parity as TP
+    TP.hs = hs
+    TP._fp32_parity(W.best_of_call(n_assets=5, n_paths=25000, n_steps=252), scheme="qe")
+
+
+def test_qe_multi_asset_matches_euler_on_gpu():
+    # both schemes price the same joint law: a 5-asset European best-of call
+    # agrees within 4 SE of the pathwise difference plus twice the schemes'
+    # time-step biases (halved dt), here on the GPU's FP64 paths
+    _say("QE vs Euler European best-of call N=5 P=100000 n=32/64, fp64")
+    P = 100000
+    price = {}
+    for scheme in ("euler", "qe"):
+        for n in (32, 64):
+            w = W.best_of_call(n_assets=5, n_paths=P, n_steps=n, mask=0)
+            w["option"]["style"] = "european"
+            f = hs.path_features(w["model"], w["corr"], 1.0, P, n, seed=w["seed"],
+                                 precision="fp64", scheme=scheme).cpu().numpy()
+            price[scheme, n] = np.exp(-w["model"]["r"]) * np.maximum(f[-1, :, 0] - 100.0, 0.0)
+    d = price["qe", 64] - price["euler", 64]
+    se = d.std(ddof=1) / np.sqrt(P)
+    bias = sum(abs(price[s, 64].mean() - price[s, 32].mean()) for s in ("euler", "qe"))
+    _say("  QE - Euler %.4f, SE %.4f, bias %.4f" % (d.mean(), se, bias))
+    assert abs(d.mean()) <= 4 * se + 2 * bias
