@@ -1,17 +1,23 @@
 """Throughput of full Greek sets on one MI355X.
 
-A step is one whole Greek set of the 5-asset Heston best-of American call
-(25,000 paths x 252 steps, 28 bump-and-revalue scenarios with common random
-numbers, FP32 paths / FP64 regression): path kernel, Gram kernel, backward
-sweep, results back on the host, Greeks.  Each pass of the set replays a
-cached HIP graph.  Inputs are seeded and synthetic and already in HBM; only
-the few-KB parameter tables go up and the scenario prices come back.
+A step is one whole Greek set of the 10-asset Heston best-of American call
+(200,000 paths x 252 steps, 78 bump-and-revalue scenarios with common random
+numbers: base, 2 x 10 spot, 10 v0, maturity, rate and 45 correlation bumps;
+FP32 paths / FP64 regression): path kernel, Gram kernel, backward sweep,
+results back on the host, Greeks.  The launch shape is autotuned first and
+each pass of the set replays a cached HIP graph.  Inputs are seeded and
+synthetic and already in HBM; only the few-KB parameter tables go up and the
+scenario prices come back.  The 5-asset 25,000 x 252 set (28 scenarios) is
+timed after it as a secondary figure.
 
-Printed: one JSON line with the metric (Greek-set path-steps/s), the roofline
-of the dominant kernel (HIP-event times on the library's stream), the FP64
-oracle timed on the host cores, the accuracy of the timed results against the
-oracle, the plain per-scenario FP64 GPU comparator, and p50/p99 request latency
-of the serving loop under a Poisson stream of mixed-size requests.
+Printed: one JSON line with the metric (Greek-set path-steps/s; the median and
+spread of the per-set times beside the mean), the roofline of the dominant
+kernel (HIP-event times on the library's stream), the FP64 oracle timed on the
+host cores (one thread and all cores) on a sample of whole scenarios, the
+accuracy of the timed results against the oracle on those scenarios, the plain
+per-scenario FP64 GPU comparator, and p50/p99 request latency of the serving
+loop under a Poisson stream of mixed-size requests.  --serve-sweep instead
+runs only the serving loop at offered loads 0.5, 0.8 and 0.95.
 """
 import argparse
 import hashlib
@@ -32,8 +38,9 @@ METRIC = "Greek-set path-steps/s at <=1e-4 rel err vs FP64; p50/p99 request late
 HBM_PEAK_GBS = 8000.0
 # non-packed VALU lane-op slots per second: 256 CUs x 64 lanes x 2.4 GHz
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
-KERNEL_SRC = os.path.join(ROOT, "paper_2206_03719_amd", "csrc", "hs_kernels.hip")
-COUNTERS = os.path.join(ROOT, "profiles", "greekset_bestof5_25000x252_hbm_counters.txt")
+CSRC = os.path.join(ROOT, "paper_2206_03719_amd", "csrc")
+COUNTERS = {10: os.path.join(ROOT, "profiles", "greekset_bestof10_200000x252_hbm_counters.txt"),
+            5: os.path.join(ROOT, "profiles", "greekset_bestof5_25000x252_hbm_counters.txt")}
 # device kernel names (prefixes) of the three stages
 KERNEL_NAMES = {"paths": "k_paths", "gram": "k_gram", "sweep": "k_sweep_cluster"}
 
@@ -99,6 +106,17 @@ def path_kernel_slots(N, P, n, mask):
     return per_path_step * P * n
 
 
+def kernel_source_sha256():
+    """SHA-256 over the device sources (hs_*.hip and the headers they include),
+    in name order: the kernel version a counter summary was taken on."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
 def read_counters(path):
     """HBM bytes per dispatch from the committed counter summary, or None when
     it is missing or was taken on another version of the kernel source."""
@@ -106,7 +124,7 @@ def read_counters(path):
         lines = open(path).read().splitlines()
     except OSError:
         return None
-    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    src = kernel_source_sha256()
     fields = dict(l.split(":", 1) for l in lines if ":" in l and not l.startswith(("#", " ")))
     if fields.get("kernel_source_sha256", "").strip() != src:
         return None
@@ -122,6 +140,129 @@ def read_counters(path):
     return out
 
 
+def greek_set_leg(hs, torch, w, steps, warmup, graph, autotune, counters_path):
+    """Times `steps` whole Greek sets of workload w (after `warmup` untimed
+    ones) and returns the figures: the mean over the bracketed run, the median
+    and spread of the per-set times, per-kernel device times from HIP events
+    on the library's stream (the same sets launched eagerly), and the roofline
+    of the dominant kernel."""
+    N, P, n = len(w["model"]["S0"]), w["n_paths"], w["n_steps"]
+    S = hs.num_scenarios(N, w["bumps"]["mask"])
+    nbytes = hs.workspace_bytes(w["model"], w["option"], P, n, w["bumps"], "fp32")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()  # a non-null stream: graph replay needs one
+
+    def step(timing=False):
+        return hs.price_greeks(w["model"], w["corr"], w["option"], P, n, w["bumps"],
+                               seed=w["seed"], precision="fp32", workspace=ws, stream=stream,
+                               timing=timing, graph=graph and not timing)
+
+    tuned = None
+    if autotune:
+        tuned = hs.autotune(w["model"], w["corr"], w["option"], P, n, w["bumps"], seed=w["seed"],
+                            workspace=ws, stream=stream, repeats=3)
+        log("%s: autotuned, %.3f ms per Greek set" % (w["name"], tuned))
+    log("%s: warmup %d" % (w["name"], warmup))
+    for _ in range(warmup):
+        res = step()
+    torch.cuda.synchronize()
+    log("%s: timing %d Greek sets%s" % (w["name"], steps, " (graph replay)" if graph else ""))
+    per = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ta = time.perf_counter()
+        res = step()  # returns with the results on the host (stream synchronized)
+        per.append((time.perf_counter() - ta) * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / steps
+    path_steps = S * P * n
+    value = path_steps / (ms * 1e-3)
+    log("%s: %.3f ms per Greek set (median %.3f), %.3e path-steps/s"
+        % (w["name"], ms, float(np.median(per)), value))
+
+    # per-kernel device times: the same sets launched eagerly with HIP events
+    # around each stage on the library's stream
+    kt = {"paths": [], "gram": [], "sweep": []}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = step(timing=True)
+        kt["paths"].append(r["t_paths_ms"])
+        kt["gram"].append(r["t_gram_ms"])
+        kt["sweep"].append(r["t_sweep_ms"])
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / steps
+    kms = {k: float(np.mean(v)) for k, v in kt.items()}
+    log("%s: kernel ms (mean of %d): %s; eager set %.3f ms"
+        % (w["name"], steps, json.dumps(kms), ms_eager))
+    # algorithmic bytes per launch: features are 8 B (FP32 U, A) per path-step;
+    # the path kernel writes them once, the Gram kernel reads dates 1..n-1,
+    # the sweep reads every date once
+    alg = {"paths": S * P * n * 8.0, "gram": S * P * (n - 1) * 8.0, "sweep": S * P * n * 8.0}
+    slots = path_kernel_slots(N, P, n, w["bumps"]["mask"])
+    traffic = read_counters(counters_path)
+    per_kernel = {}
+    for k in kms:
+        sec = kms[k] * 1e-3
+        per_kernel[k] = {"kernel": KERNEL_NAMES[k], "ms": round(kms[k], 4),
+                         "alg_bytes": alg[k], "hbm_GBs": round(alg[k] / sec / 1e9, 1),
+                         "hbm_frac": round(alg[k] / sec / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic_bytes": traffic.get(k) if traffic else None}
+    per_kernel["paths"]["alu_slots"] = slots
+    per_kernel["paths"]["alu_frac"] = round(slots / (kms["paths"] * 1e-3) / ALU_PEAK_OPS, 4)
+    dom = max(kms, key=kms.get)
+    sec = kms[dom] * 1e-3
+    if dom == "paths":
+        # the path kernel is bound by VALU and transcendental issue, not HBM
+        roofline = {"bound": "alu", "kernel": KERNEL_NAMES[dom],
+                    "achieved": round(slots / sec / 1e12, 3), "peak": ALU_PEAK_OPS / 1e12,
+                    "unit": "Tslot/s", "frac": round(slots / sec / ALU_PEAK_OPS, 4)}
+    else:
+        achieved = alg[dom] / sec / 1e9
+        roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roofline["traffic"] = traffic.get(dom) if traffic else None
+    roofline["kernel_ms"] = round(kms[dom], 4)
+    roofline["per_kernel"] = per_kernel
+    spread = {"median_ms": float(np.median(per)), "min_ms": float(np.min(per)),
+              "max_ms": float(np.max(per)), "p10_ms": float(np.percentile(per, 10)),
+              "p90_ms": float(np.percentile(per, 90)), "stdev_ms": float(np.std(per, ddof=1))
+              if len(per) > 1 else 0.0, "sets": len(per),
+              "median_path_steps_per_s": path_steps / (float(np.median(per)) * 1e-3)}
+    del ws
+    return {"value": value, "ms": ms, "spread": spread, "kernel_ms": kms, "eager_ms": ms_eager,
+            "roofline": roofline, "res": res, "S": S, "path_steps": path_steps,
+            "autotuned_ms": tuned, "stream": stream}
+
+
+def cpu_baseline_leg(w, scen, threads_all, res):
+    """The FP64 oracle on the host cores over whole scenarios of the Greek set
+    (the regression couples all paths of a scenario, so a prefix of paths would
+    be another problem): the scenarios `scen` at all cores, and the first of
+    them at one thread.  Also the accuracy of the GPU's timed prices on them."""
+    import oracle
+    N, P, n = len(w["model"]["S0"]), w["n_paths"], w["n_steps"]
+    nob = dict(w["bumps"], mask=0)
+    models = per_scenario_models(w)
+    out = {}
+    prices = {}
+    for label, threads, ss in (("all", threads_all, scen), ("one", 1, scen[:1])):
+        log("cpu baseline: FP64 oracle, %d scenario(s) of %d x %d x %d, %d thread(s)"
+            % (len(ss), N, P, n, threads))
+        t0 = time.perf_counter()
+        for s in ss:
+            m, C, opt = models[s]
+            prices[s] = oracle.price_greeks(m, C, opt, P, n, nob, w["seed"],
+                                            nthreads=threads)["price"]
+        sec = time.perf_counter() - t0
+        out[label] = {"value": len(ss) * P * n / sec, "seconds": sec, "threads": threads,
+                      "scenarios": list(ss)}
+    err = {s: abs(res["scenario_price"][s] - p) / abs(p) for s, p in prices.items()}
+    return out, {"max_price_rel_err": max(err.values()), "scenarios_checked": sorted(err)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,9 +271,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--workload", choices=("bestof10", "bestof5"), default="bestof10")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="only the serving loop: --serve-requests (default 1000 here) requests "
+                         "at offered loads 0.5, 0.8 and 0.95 of the saturated capacity")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (HBM counter calibration)")
@@ -163,113 +309,52 @@ def main():
     if args.table1:
         table1_leg(hs, torch, args)
         return
-    w = W.best_of_call(n_assets=5, n_paths=25000, n_steps=252, precision="fp32")
-    N, P, n = 5, w["n_paths"], w["n_steps"]
-    S = hs.num_scenarios(N, w["bumps"]["mask"])
-    nbytes = hs.workspace_bytes(w["model"], w["option"], P, n, w["bumps"], "fp32")
-    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.Stream()  # a non-null stream: graph replay needs one
+    if args.serve_sweep:
+        n_req = args.serve_requests if "--serve-requests" in sys.argv else 1000
+        for line in serve_sweep(hs, torch, n_req):
+            print(json.dumps(line), flush=True)
+        return
     graph = not args.no_graph
-
-    def step(timing=False):
-        return hs.price_greeks(w["model"], w["corr"], w["option"], P, n, w["bumps"],
-                               seed=w["seed"], precision="fp32", workspace=ws, stream=stream,
-                               timing=timing, graph=graph and not timing)
-
-    if args.autotune:
-        best = hs.autotune(w["model"], w["corr"], w["option"], P, n, w["bumps"], seed=w["seed"],
-                           workspace=ws, stream=stream, repeats=3)
-        log("autotuned: %.3f ms per Greek set" % best)
-    log("warmup %d" % args.warmup)
-    for _ in range(args.warmup):
-        res = step()
-    torch.cuda.synchronize()
-    log("timing %d Greek sets%s" % (args.steps, " (graph replay)" if graph else ""))
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    path_steps = S * P * n
-    value = path_steps / (ms * 1e-3)
-    log("%.3f ms per Greek set, %.3e path-steps/s" % (ms, value))
-
-    # per-kernel device times: the same K Greek sets launched eagerly with HIP
-    # events around each stage on the library's stream
-    kt = {"paths": [], "gram": [], "sweep": []}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = step(timing=True)
-        kt["paths"].append(r["t_paths_ms"])
-        kt["gram"].append(r["t_gram_ms"])
-        kt["sweep"].append(r["t_sweep_ms"])
-    torch.cuda.synchronize()
-    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
-    kms = {k: float(np.mean(v)) for k, v in kt.items()}
-    log("kernel ms (mean of %d): %s; eager set %.3f ms" % (args.steps, json.dumps(kms), ms_eager))
-    # algorithmic bytes per launch: features are 8 B (FP32 U, A) per path-step;
-    # the path kernel writes them once, the Gram kernel reads dates 1..n-1,
-    # the sweep reads every date once
-    alg = {"paths": S * P * n * 8.0, "gram": S * P * (n - 1) * 8.0, "sweep": S * P * n * 8.0}
-    slots = path_kernel_slots(N, P, n, w["bumps"]["mask"])
-    traffic = read_counters(COUNTERS)
-    per_kernel = {}
-    for k in kms:
-        sec = kms[k] * 1e-3
-        per_kernel[k] = {"kernel": KERNEL_NAMES[k], "ms": round(kms[k], 4),
-                         "alg_bytes": alg[k], "hbm_GBs": round(alg[k] / sec / 1e9, 1),
-                         "hbm_frac": round(alg[k] / sec / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic_bytes": traffic.get(k) if traffic else None}
-    per_kernel["paths"]["alu_slots"] = slots
-    per_kernel["paths"]["alu_frac"] = round(slots / (kms["paths"] * 1e-3) / ALU_PEAK_OPS, 4)
-    dom = max(kms, key=kms.get)
-    sec = kms[dom] * 1e-3
-    if dom == "paths":
-        # the path kernel is bound by VALU and transcendental issue, not HBM
-        roofline = {"bound": "alu", "kernel": KERNEL_NAMES[dom],
-                    "achieved": round(slots / sec / 1e12, 3), "peak": ALU_PEAK_OPS / 1e12,
-                    "unit": "Tslot/s", "frac": round(slots / sec / ALU_PEAK_OPS, 4)}
+    if args.workload == "bestof10":
+        w = W.best_of_call(n_assets=10, n_paths=200_000, n_steps=252, precision="fp32")
     else:
-        achieved = alg[dom] / sec / 1e9
-        roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    roofline["traffic"] = traffic.get(dom) if traffic else None
-    roofline["kernel_ms"] = round(kms[dom], 4)
-    roofline["per_kernel"] = per_kernel
-
+        w = W.best_of_call(n_assets=5, n_paths=25_000, n_steps=252, precision="fp32")
+    N, P, n = len(w["model"]["S0"]), w["n_paths"], w["n_steps"]
+    lg = greek_set_leg(hs, torch, w, args.steps, args.warmup, graph, not args.no_autotune,
+                       COUNTERS[N])
+    S, ms, value, res = lg["S"], lg["ms"], lg["value"], lg["res"]
     out = {"metric": METRIC, "value": value, "unit": "path-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "heston-bestof-call-5x25000x252 greek set (28 scenarios)",
+           "config": {"workload": "%s greek set (%d scenarios)" % (w["name"], S),
                       "n_assets": N, "n_paths": P, "n_steps": n, "n_scenarios": S,
                       "precision": "f32 paths, f64 regression", "seed": w["seed"],
-                      "graph": graph, "elements_per_s": value * N,
-                      "eager_ms_per_step": ms_eager},
-           "roofline": roofline}
+                      "graph": graph, "autotuned": not args.no_autotune,
+                      "elements_per_s": value * N, "eager_ms_per_step": lg["eager_ms"],
+                      "autotune_best_ms": lg["autotuned_ms"]},
+           "timing": lg["spread"],
+           "roofline": lg["roofline"]}
 
     if not args.no_cpu_baseline:
-        import oracle
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-        log("cpu baseline: FP64 oracle, full Greek set, %d threads" % threads)
-        t0 = time.perf_counter()
-        o = oracle.price_greeks(w["model"], w["corr"], w["option"], P, n, w["bumps"], w["seed"],
-                                nthreads=threads)
-        t1 = time.perf_counter()
-        out["cpu_baseline"] = {"value": path_steps / (t1 - t0), "unit": "path-steps/s",
+        # base, spot up of asset 0, v0 of asset 0, correlation (0, 1) at all
+        # cores; the base alone at one thread
+        scen = [0, 1, 1 + 2 * N, 3 + 3 * N] if N > 1 else [0]
+        cb, acc = cpu_baseline_leg(w, scen, threads, res)
+        out["cpu_baseline"] = {"value": cb["all"]["value"], "unit": "path-steps/s",
                                "cores": threads, "kind": "oracle",
-                               "sample": "the whole 28-scenario Greek set (25k paths x 252 "
-                                         "steps, FP64): the regression couples all paths",
-                               "seconds": t1 - t0, "cpu": cpu_model(),
-                               "host_cpus": os.cpu_count()}
-        err = np.abs(res["scenario_price"] - o["scenario_price"]) / np.abs(o["scenario_price"])
-        acc = {"max_price_rel_err": float(err.max()),
-               "delta_max_rel_err": float(np.max(np.abs(res["delta"] - o["delta"]) /
-                                                 np.abs(o["delta"])))}
+                               "sample": "scenarios %s of the set (base, spot up and v0 of "
+                                         "asset 0, correlation (0, 1)), each whole: %d paths x "
+                                         "%d steps in FP64; the regression couples all paths"
+                                         % (scen, P, n),
+                               "seconds": cb["all"]["seconds"], "cpu": cpu_model(),
+                               "host_cpus": os.cpu_count(),
+                               "one_thread": {"value": cb["one"]["value"],
+                                              "seconds": cb["one"]["seconds"],
+                                              "scenarios": cb["one"]["scenarios"]}}
         out["accuracy_vs_fp64_oracle"] = acc
-        out["valid"] = bool(err.max() <= 1e-4)
+        out["valid"] = bool(acc["max_price_rel_err"] <= 1e-4)
         log("accuracy: %s" % json.dumps(acc))
 
     if not args.no_comparator:
@@ -278,6 +363,7 @@ def main():
         nob = dict(w["bumps"], mask=0)
         wsb = max(hs.workspace_bytes(mm, oo, P, n, nob, "fp64") for mm, _, oo in models)
         ws64 = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        stream = lg["stream"]
 
         def plain():
             return [hs.price_greeks(mm, CC, oo, P, n, nob, seed=w["seed"], precision="fp64",
@@ -290,13 +376,27 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         out["comparator_fp64_per_scenario"] = {
-            "value": path_steps / (t1 - t0), "unit": "path-steps/s", "ms": (t1 - t0) * 1e3,
-            "speedup_of_batched": (t1 - t0) * 1e3 / ms}
+            "value": lg["path_steps"] / (t1 - t0), "unit": "path-steps/s",
+            "ms": (t1 - t0) * 1e3, "speedup_of_batched": (t1 - t0) * 1e3 / ms,
+            "max_rel_diff_vs_batched": float(np.max(np.abs(np.array(prices) -
+                                                           res["scenario_price"]) /
+                                                    np.abs(np.array(prices))))}
         del ws64
         log("comparator %.2f ms" % ((t1 - t0) * 1e3))
 
+    if not args.no_secondary and args.workload == "bestof10":
+        w5 = W.best_of_call(n_assets=5, n_paths=25_000, n_steps=252, precision="fp32")
+        l5 = greek_set_leg(hs, torch, w5, max(args.steps, 10), args.warmup, graph, False,
+                           COUNTERS[5])
+        out["secondary"] = {"workload": "%s greek set (%d scenarios)" % (w5["name"], l5["S"]),
+                            "value": l5["value"], "unit": "path-steps/s", "ms_per_step": l5["ms"],
+                            "timing": l5["spread"], "kernel_ms": l5["kernel_ms"],
+                            "roofline": {k: v for k, v in l5["roofline"].items()
+                                         if k != "per_kernel"}}
+        torch.cuda.empty_cache()
+
     if not args.no_serve:
-        out["latency"] = serve_leg(hs, torch, args.serve_requests)
+        out["latency"] = serve_leg(hs, torch, args.serve_requests, 0.8)
         log("serving: %s" % json.dumps(out["latency"]))
 
     print(json.dumps(out), flush=True)
@@ -395,57 +495,96 @@ def cpu_model():
     return "unknown"
 
 
-def serve_leg(hs, torch, n_req):
+def _saturated(hs, srv, n_req):
+    """All requests queued at once: requests/s and path-steps/s at saturation."""
+    reqs = [r for _, r in W.serving_stream(n_req, 1.0, seed=11)]
+    t0 = time.perf_counter()
+    tickets = [srv.submit(r) for r in reqs]
+    done = {}
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                p = srv.poll(t)
+                if p is not None:
+                    done[t] = p
+        time.sleep(0.001)
+    t_sat = time.perf_counter() - t0
+    steps = sum(hs.num_scenarios(len(r["model"]["S0"]), 31) * r["n_paths"] * r["n_steps"]
+                for r in reqs)
+    return len(reqs) / t_sat, steps / t_sat
+
+
+def _poisson_run(hs, srv, n_req, rate, seed):
+    """A Poisson stream of n_req requests at `rate` per second: latency from
+    submit to result of each, and the path-steps/s the run sustained."""
+    stream = W.serving_stream(n_req, rate, seed=seed)
+    lat = []
+    t0 = time.perf_counter()
+    pending = {}
+    i = 0
+    while i < len(stream) or pending:
+        now = time.perf_counter() - t0
+        while i < len(stream) and stream[i][0] <= now:
+            pending[srv.submit(stream[i][1])] = True
+            i += 1
+        for t in list(pending):
+            p = srv.poll(t)
+            if p is not None:
+                lat.append(p[1])
+                del pending[t]
+        time.sleep(0.0005)
+    t_run = time.perf_counter() - t0
+    steps = sum(hs.num_scenarios(len(r["model"]["S0"]), 31) * r["n_paths"] * r["n_steps"]
+                for _, r in stream)
+    lat = np.array(lat) * 1e3
+    return {"requests": len(stream), "offered_req_per_s": rate,
+            "path_steps_per_s": steps / t_run, "p50_ms": float(np.percentile(lat, 50)),
+            "p90_ms": float(np.percentile(lat, 90)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "seconds": t_run}
+
+
+def _server(hs, torch, slots=4):
+    free, total = torch.cuda.mem_get_info()
+    pool = int(min(free * 0.7, 160e9))
+    return hs.Server(pool, max_slots=slots), pool
+
+
+def serve_leg(hs, torch, n_req, load):
     """Poisson stream of mixed-size full-Greek-set requests (assets U{1..20},
     paths U[10k, 400k], steps U{52,126,252,504}) through the serving loop.
     First the saturated capacity (all requests queued at once), then a
-    Poisson stream at 0.8 of it: p50/p99 latency from submit to result."""
-    free, total = torch.cuda.mem_get_info()
-    pool = int(min(free * 0.7, 160e9))
-    srv = hs.Server(pool, max_slots=4)
+    Poisson stream at `load` of it: p50/p99 latency from submit to result."""
+    srv, pool = _server(hs, torch)
     try:
-        reqs = [r for _, r in W.serving_stream(n_req, 1.0, seed=11)]
-        t0 = time.perf_counter()
-        tickets = [srv.submit(r) for r in reqs]
-        done = {}
-        while len(done) < len(tickets):
-            for t in tickets:
-                if t not in done:
-                    p = srv.poll(t)
-                    if p is not None:
-                        done[t] = p
-            time.sleep(0.001)
-        t_sat = time.perf_counter() - t0
-        steps_sat = sum(hs.num_scenarios(len(r["model"]["S0"]), 31) * r["n_paths"] * r["n_steps"]
-                        for r in reqs)
-        cap = len(reqs) / t_sat
-        rate = 0.8 * cap
-        stream = W.serving_stream(n_req, rate, seed=12)
-        lat = []
-        t0 = time.perf_counter()
-        pending = {}
-        i = 0
-        while i < len(stream) or pending:
-            now = time.perf_counter() - t0
-            while i < len(stream) and stream[i][0] <= now:
-                pending[srv.submit(stream[i][1])] = True
-                i += 1
-            for t in list(pending):
-                p = srv.poll(t)
-                if p is not None:
-                    lat.append(p[1])
-                    del pending[t]
-            time.sleep(0.0005)
-        t_run = time.perf_counter() - t0
-        steps_run = sum(hs.num_scenarios(len(r["model"]["S0"]), 31) * r["n_paths"] * r["n_steps"]
-                        for _, r in stream)
+        cap, sat_steps = _saturated(hs, srv, n_req)
+        run = _poisson_run(hs, srv, n_req, load * cap, seed=12)
         st = srv.stats()
-        return {"requests": len(stream), "offered_load": 0.8,
-                "saturated_req_per_s": cap, "saturated_path_steps_per_s": steps_sat / t_sat,
-                "path_steps_per_s": steps_run / t_run,
-                "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "pool_GB": pool / 1e9, "pool_peak_GB": st["pool_peak"] / 1e9, "slots": 4}
+        return dict(run, offered_load=load, saturated_req_per_s=cap,
+                    saturated_path_steps_per_s=sat_steps, pool_GB=pool / 1e9,
+                    pool_peak_GB=st["pool_peak"] / 1e9, slots=4)
+    finally:
+        srv.close()
+
+
+def serve_sweep(hs, torch, n_req):
+    """The serving loop at offered loads 0.5, 0.8 and 0.95 of its saturated
+    capacity, n_req requests each: one JSON line per load."""
+    srv, pool = _server(hs, torch)
+    try:
+        log("serve sweep: saturated capacity over %d requests" % n_req)
+        cap, sat_steps = _saturated(hs, srv, n_req)
+        log("serve sweep: %.2f requests/s, %.3e path-steps/s saturated" % (cap, sat_steps))
+        out = []
+        for i, load in enumerate((0.5, 0.8, 0.95)):
+            log("serve sweep: offered load %.2f" % load)
+            run = _poisson_run(hs, srv, n_req, load * cap, seed=20 + i)
+            line = dict(run, serve_sweep=True, offered_load=load, saturated_req_per_s=cap,
+                        saturated_path_steps_per_s=sat_steps, pool_GB=pool / 1e9)
+            log(json.dumps(line))
+            out.append(line)
+        st = srv.stats()
+        out.append({"serve_sweep_stats": st})
+        return out
     finally:
         srv.close()
 
