@@ -92,5 +92,5 @@ def compare(gval, oval, terms, unit, V_base, dcf_rows):
     se = greek_se(dcf_rows, terms) if dcf_rows is not None else 0.0
     floor = 1e-8 * abs(V_base) / unit
     den = max(abs(oval), floor, se)
-    return {"gpu": gval, "oracle": oval, "se": se, "noise_level": abs(oval) < se,
-            "rel_err": abs(gval - oval) / den}
+    return {"gpu": float(gval), "oracle": float(oval), "se": se,
+            "noise_level": bool(abs(oval) < se), "rel_err": float(abs(gval - oval) / den)}

@@ -128,6 +128,10 @@ def test_ten_assets_200k_greek_set():
     rep = {"max_price_rel_err": max(errs.values()), "scenarios_checked": pick,
            "max_greek_rel_err": max(v["rel_err"] for v in greeks.values()), "greeks": greeks}
     report("10x200000x252_fp32", rep)
+    for k, v in greeks.items():
+        _say("  %-9s gpu %.8e oracle %.8e se %.2e rel err %.2e%s"
+             % (k, v["gpu"], v["oracle"], v["se"], v["rel_err"],
+                " (noise level)" if v["noise_level"] else ""))
     assert rep["max_price_rel_err"] <= 1e-4
     bad = {k: v["rel_err"] for k, v in greeks.items() if v["rel_err"] > GB.BAR}
     assert not bad, bad

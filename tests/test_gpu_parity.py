@@ -197,6 +197,10 @@ def _fp32_parity(w, scheme="euler"):
     report["noise_level_greeks"] = [k for k, v in greeks.items() if v["noise_level"]]
     report["greeks"] = greeks
     _say("  fp32 " + json.dumps({k: v for k, v in report.items() if k != "greeks"}))
+    for k, v in greeks.items():
+        _say("  %-9s gpu %.8e oracle %.8e se %.2e rel err %.2e%s"
+             % (k, v["gpu"], v["oracle"], v["se"], v["rel_err"],
+                " (noise level)" if v["noise_level"] else ""))
     os.makedirs("gpurun_out", exist_ok=True)
     with open(os.path.join("gpurun_out", "fp32_parity_%s_%s.json" % (w["name"], scheme)), "w") as f:
         json.dump(report, f, indent=1)
