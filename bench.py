@@ -160,7 +160,7 @@ def greek_set_leg(hs, torch, w, steps, warmup, graph, autotune, counters_path):
     tuned = None
     if autotune:
         tuned = hs.autotune(w["model"], w["corr"], w["option"], P, n, w["bumps"], seed=w["seed"],
-                            workspace=ws, stream=stream, repeats=3)
+                            workspace=ws, stream=stream, repeats=3, graph=graph)
         log("%s: autotuned, %.3f ms per Greek set" % (w["name"], tuned))
     log("%s: warmup %d" % (w["name"], warmup))
     for _ in range(warmup):
@@ -561,7 +561,9 @@ def serve_leg(hs, torch, n_req, load):
         st = srv.stats()
         return dict(run, offered_load=load, saturated_req_per_s=cap,
                     saturated_path_steps_per_s=sat_steps, pool_GB=pool / 1e9,
-                    pool_peak_GB=st["pool_peak"] / 1e9, slots=4)
+                    pool_peak_GB=st["pool_peak"] / 1e9, slots=st["slots"],
+                    device_max_concurrent=st["device_max_concurrent"],
+                    device_overlap_s=st["device_overlap_s"])
     finally:
         srv.close()
 

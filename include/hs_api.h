@@ -94,16 +94,20 @@ typedef int32_t hs_status;
 /* opts.scheme: the time step of the Heston paths (Sec. 2.2 and 2.2.1).
  *   EULER_FT: full-truncation Euler in log price, v+ = max(v, 0):
  *     X += (r - v+/2) dt + sqrt(v+ dt) Z^S;
- *     v += kappa (theta - v+) dt + xi sqrt(v+ dt) (rho Z^S + sqrt(1-rho^2) eta).
+ *     v += kappa (theta - v+) dt + xi sqrt(v+ dt) Z^v.
  *   QE: Andersen's quadratic-exponential step, the benchmark's own scheme:
  *     the next variance matches the CIR conditional mean m and variance s^2
- *     (psi = s^2/m^2 <= 1.5: a (b + eta)^2; else 0 with probability
+ *     (psi = s^2/m^2 <= 1.5: a (b + Z^v)^2; else 0 with probability
  *     p = (psi-1)/(psi+1), otherwise exponential with mean m/(1-p), drawn
- *     with the uniform Phi(eta)); log price
- *     X += r dt + K0 + K1 v + K2 v' + sqrt(K3 v + K4 v') Z^S with
- *     gamma1 = gamma2 = 1/2.  Needs xi_i > 0 or rho_i = 0 for every asset.
- * Z^S = L eps in both, with (eps, eta) the Box-Muller pairs of the same
- * Philox counters, so both schemes consume identical random numbers. */
+ *     with the uniform Phi(Z^v)); log price
+ *     X += r dt + K0 + K1 v + K2 v' + sqrt(K3 v + K4 v') Z^x with
+ *     gamma1 = gamma2 = 1/2 and Z^x = sqrt(1-rho^2) Z^S - rho eta, the part
+ *     of the spot shock orthogonal to the variance shock (K2 v' carries the
+ *     rest).  Needs xi_i > 0 or rho_i = 0 for every asset.
+ * In both, Z^S = L eps and Z^v = rho Z^S + sqrt(1-rho^2) eta, with (eps, eta)
+ * the Box-Muller pairs of the same Philox counters: both schemes consume
+ * identical random numbers, and the spot shocks of assets i and j correlate
+ * as C_ij under either. */
 #define HS_SCHEME_EULER_FT 0
 #define HS_SCHEME_QE 1
 
@@ -161,9 +165,15 @@ typedef struct hs_bumps {
 
 typedef struct hs_opts {
     int32_t precision;       /* HS_FP64 | HS_FP32_PATHS                          */
-    int32_t waves_per_block; /* path kernel: 0 = planner's choice, else 1..8 waves
-                                of 64 paths' scenario groups per block (FP64 at
-                                13-16 assets runs at most 4)                       */
+    int32_t waves_per_block; /* path kernel launch shape: 0 = the tuned or
+                                planner's choice, else 1..8 waves per block (FP64 at
+                                13-16 assets runs at most 4).  A block always follows
+                                64 paths (one per lane) through every step; its waves
+                                split the scenario groups, so this is the library's
+                                paths-per-block and work-per-wave knob.  Steps are
+                                not tiled: each step needs the previous one's state,
+                                so a block runs them in order with the state in
+                                registers.  Never changes results.                 */
     uint64_t seed;           /* Philox key                                         */
     uint32_t flags;          /* HS_FLAG_*                                          */
     int32_t sweep_mode;      /* backward sweep: 0 = automatic (cluster when it fits the
@@ -212,12 +222,14 @@ typedef struct hs_greeks {
 
 /* Number of scenarios in the Greek set that bumps->mask describes
  * (1 + 2N + N + 1 + 1 + N(N-1)/2 for HS_BUMP_ALL).  -1 if n_assets is out of
- * range or bumps is NULL. */
+ * range or bumps is NULL.  (A sizing query of this interface: the paper asks
+ * for per-asset sensitivities, Sec. 2.2, and names no call of its own.) */
 int64_t hs_num_scenarios(int32_t n_assets, const hs_bumps *bumps);
 
 /* Device workspace bytes hs_price_greeks needs to run the whole Greek set in
  * one pass (features of every scenario resident at once).  0 on invalid
- * arguments (see hs_last_error). */
+ * arguments (see hs_last_error).  (A sizing query of this interface, so that
+ * the caller owns all device memory; the paper has no counterpart.) */
 size_t hs_workspace_bytes(const hs_model *model, const hs_option *option, int64_t n_paths,
                           int32_t n_steps, const hs_bumps *bumps, const hs_opts *opts);
 
@@ -225,7 +237,9 @@ size_t hs_workspace_bytes(const hs_model *model, const hs_option *option, int64_
  * several passes over scenario groups and, where one group's features do not
  * fit, in windows of dates that recompute the paths from checkpoints of their
  * state (same results, bit for bit).  With opts.window_dates > 0 both calls
- * size every group in windows of that many dates. */
+ * size every group in windows of that many dates.  (A sizing query of this
+ * interface; the windows answer the capacity problem that the paper meets by
+ * batching paths through on-chip memory, Sec. 4.1 and Fig. 3.) */
 size_t hs_workspace_min_bytes(const hs_model *model, const hs_option *option, int64_t n_paths,
                               int32_t n_steps, const hs_bumps *bumps, const hs_opts *opts);
 
@@ -272,18 +286,25 @@ hs_status hs_path_features(const hs_model *model, const double *corr, int64_t n_
 
 /* Autotuner of the path kernel's launch shape (waves per block, scenario-group
  * granularity) for requests shaped like this one: times each candidate
- * `repeats` times on hip_stream with the given workspace and stores the
- * fastest in a process-wide table that hs_price_greeks and the server consult
- * when opts.waves_per_block == 0.  These parameters never change results (the
- * backward-sweep shape, which does fix the order of FP64 sums, depends only
- * on n_paths, the scenario count and the precision, and is not tuned).  *best_ms (host, may be NULL) receives the
- * winning Greek-set time.  Same arguments and errors as hs_price_greeks. */
+ * `repeats` times on hip_stream with the given workspace, in the mode the
+ * request will run in (graph replay if opts.flags has HS_FLAG_GRAPH), and
+ * stores the fastest in a process-wide table keyed on everything that fixes
+ * the launch (assets, path and step classes, scenarios, precision, scheme,
+ * feature format, sweep mode and dates per window), which hs_price_greeks
+ * and the server consult when opts.waves_per_block == 0.  These parameters
+ * never change results (the backward-sweep shape, which does fix the order
+ * of FP64 sums, depends only on the request and is not tuned).  *best_ms
+ * (host, may be NULL) receives the winning Greek-set time.  Same arguments
+ * and errors as hs_price_greeks.  (An interface call of this library: the
+ * paper tunes its FPGA design by hand, Sec. 4.) */
 hs_status hs_autotune(const hs_model *model, const double *corr, const hs_option *option,
                       int64_t n_paths, int32_t n_steps, const hs_bumps *bumps,
                       const hs_opts *opts, void *d_workspace, size_t workspace_bytes,
                       void *hip_stream, int32_t repeats, double *best_ms);
 
-/* Diagnostics for bit-exactness checks of the device random numbers.
+/* Diagnostics for bit-exactness checks of the device random numbers (the
+ * paper streams precomputed random numbers into its kernel, Sec. 4; these
+ * expose the ones this library draws on the device, for tests).
  * hs_philox_words: d_out (device uint32) receives, for path p in
  * [0, n_paths), step k in [0, n_steps) and block j in [0, n_blocks), the four
  * Philox4x32-10 words of counter (p mod 2^32, k, j, p >> 32) under key
@@ -297,13 +318,18 @@ hs_status hs_normals(uint64_t seed, int32_t n_assets, int64_t n_paths, int32_t n
                      int32_t precision, void *d_eps, void *d_eta, void *hip_stream);
 
 /* ---------------------------------------------------------------------------
- * Serving: a continuous-batching request loop.  A server owns a caller-
- * provided device pool (its size is the HBM budget) and admits queued
- * requests in arrival order whenever a slot and enough pool memory are free;
- * admitted requests run concurrently on their own HIP streams, so a request
- * that arrives while others are on the GPU overlaps with them.  Each
- * request's results are identical, bit for bit, to the same request run
- * alone.  Requests larger than the whole pool run in several passes.
+ * Serving: a continuous-batching request loop (an interface of this library;
+ * the paper times single runs).  A server owns a caller-provided device pool
+ * (its size is the HBM budget).  An idle slot admits the first queued request
+ * whose workspace fits the free pool, so a small request may pass a large
+ * one waiting for memory; the head of the queue is passed at most
+ * 2 x max_slots times, after which the slots wait for it.  Admitted requests
+ * run on their own HIP streams: their path and Gram kernels run side by side
+ * on the device, and a backward sweep whose workgroups wait on each other
+ * runs while no other such sweep does (all its workgroups must be resident).
+ * Each request's results are identical, bit for bit, to the same request run
+ * alone.  A request larger than the pool runs in several passes in half of
+ * it (or its minimum workspace, if larger).
  */
 typedef struct hs_server hs_server;
 
@@ -320,7 +346,12 @@ typedef struct hs_request {
 typedef struct hs_server_stats {
     int64_t submitted, completed, cancelled, failed, running, queued;
     size_t pool_bytes, pool_in_use, pool_peak;
-    double path_steps_done; /* sum over completed requests of S * P * n */
+    double path_steps_done;        /* sum over completed requests of S * P * n    */
+    int32_t device_max_concurrent; /* most completed requests whose device work
+                                      (HIP events on their streams) overlapped   */
+    int32_t slots;                 /* max_slots of the server                    */
+    double device_overlap_s;       /* seconds with two or more of them on the
+                                      device at once                             */
 } hs_server_stats;
 
 /* device: HIP device ordinal; d_pool: device, pool_bytes of it (256-byte

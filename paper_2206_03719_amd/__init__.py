@@ -93,7 +93,9 @@ class ServerStats(ctypes.Structure):
                 ("cancelled", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("running", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("pool_bytes", ctypes.c_size_t), ("pool_in_use", ctypes.c_size_t),
-                ("pool_peak", ctypes.c_size_t), ("path_steps_done", ctypes.c_double)]
+                ("pool_peak", ctypes.c_size_t), ("path_steps_done", ctypes.c_double),
+                ("device_max_concurrent", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("device_overlap_s", ctypes.c_double)]
 
 
 # every symbol include/hs_api.h declares, with its ctypes signature
@@ -275,11 +277,13 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precisio
 
 
 def autotune(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="fp32",
-             workspace=None, stream=None, repeats=3, scheme="euler"):
+             workspace=None, stream=None, repeats=3, scheme="euler", graph=False):
     """Times the path kernel's launch shapes on this request class and stores
-    the fastest for later calls (hs_autotune).  Returns the best ms per set."""
+    the fastest for later calls (hs_autotune); ``graph``: time them as graph
+    replays, the way the calls will run.  Returns the best ms per set."""
     torch = _torch()
-    m = _Marshal(model, corr, option, bumps, seed, precision, scheme=scheme)
+    m = _Marshal(model, corr, option, bumps, seed, precision, FLAG_GRAPH if graph else 0,
+                 scheme=scheme)
     if workspace is None:
         nbytes = workspace_bytes(model, option, n_paths, n_steps, bumps, precision)
         workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")

@@ -66,11 +66,12 @@ int default_target_waves() { return 3072; }
 namespace {
 
 struct TuneKey {
-    int N, log2P, n_bucket, S, fp32, scheme;
+    int N, log2P, n_bucket, S, fp32, scheme, feat, sweep_mode, window, american;
     bool operator<(const TuneKey& o) const
     {
-        return std::tie(N, log2P, n_bucket, S, fp32, scheme) <
-               std::tie(o.N, o.log2P, o.n_bucket, o.S, o.fp32, o.scheme);
+        return std::tie(N, log2P, n_bucket, S, fp32, scheme, feat, sweep_mode, window, american) <
+               std::tie(o.N, o.log2P, o.n_bucket, o.S, o.fp32, o.scheme, o.feat, o.sweep_mode,
+                        o.window, o.american);
     }
 };
 
@@ -84,7 +85,8 @@ TuneKey tune_key(const Request& q)
     int nb = 0;
     while ((1 << (nb + 1)) <= q.n) ++nb;
     return {q.N, lp, nb, static_cast<int>(num_scenarios(q.N, q.bumps.mask)),
-            q.opts.precision == HS_FP32_PATHS ? 1 : 0, q.opts.scheme};
+            q.opts.precision == HS_FP32_PATHS ? 1 : 0, q.opts.scheme, q.opts.feature_format,
+            q.opts.sweep_mode, q.opts.window_dates, q.opt.style == HS_AMERICAN ? 1 : 0};
 }
 
 // ---------------------------------------------------------------------------
@@ -133,9 +135,43 @@ hipError_t enqueue_sweep(const PassLaunch& L, const LsmcArgs& la, hipStream_t st
 // Events ev[0..3] (optional) bracket the path kernel, the Gram kernel and the
 // sweep; in a windowed pass ev[1] follows the first path launch and the
 // windows (recompute, Gram, sweep) count as the sweep.
+//
+// A one-pass launch sequence in two parts: the front (status and slot fills,
+// path kernel, Gram kernel), which may run beside other requests' work, and
+// the back (the backward sweep), whose cluster workgroups wait on each other.
+hipError_t enqueue_front(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
+{
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.err_flag), 1, 0, st)) != hipSuccess)
+        return e;
+    if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.feat, L.pa, L.nchunks, L.nbg, st)) !=
+        hipSuccess)
+        return e;
+    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+    if (L.american && (e = launch_gram(L.feat, L.la, L.Sp, st)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+    if (L.cluster && (e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.ca.partials),
+                                          L.part_count, kEmptySlot, st)) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+hipError_t enqueue_back(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
+{
+    hipError_t e;
+    if ((e = enqueue_sweep(L, L.la, st)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
 hipError_t enqueue_pass(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
 {
     hipError_t e;
+    if (L.window == 0) {
+        if ((e = enqueue_front(L, st, ev)) != hipSuccess) return e;
+        return enqueue_back(L, st, ev);
+    }
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
     if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(L.err_flag), 1, 0, st)) != hipSuccess)
         return e;
@@ -144,18 +180,6 @@ hipError_t enqueue_pass(const PassLaunch& L, hipStream_t st, hipEvent_t* ev)
                                            L.part_count, kEmptySlot, st)
                          : hipSuccess;
     };
-    if (L.window == 0) {
-        if ((e = launch_paths(L.fp32, L.nmax, L.scheme, L.feat, L.pa, L.nchunks, L.nbg, st)) !=
-            hipSuccess)
-            return e;
-        if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-        if (L.american && (e = launch_gram(L.feat, L.la, L.Sp, st)) != hipSuccess) return e;
-        if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-        if ((e = fill_slots()) != hipSuccess) return e;
-        if ((e = enqueue_sweep(L, L.la, st)) != hipSuccess) return e;
-        if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
-        return hipSuccess;
-    }
     // checkpoint-recompute: every step once, keeping the checkpoints and the
     // last window's features; then window by window from the last date back,
     // recomputing each earlier window's features from its checkpoint
@@ -274,7 +298,7 @@ void store_tuned_shape(const Request& q, const Tune& t)
 }
 
 hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream_t st,
-                        RunResult& res, const Tune* tune)
+                        RunResult& res, const Tune* tune, bool shared)
 {
     std::vector<Scenario> sc;
     hs_status rc = expand_scenarios(q, sc);
@@ -302,14 +326,17 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
 
     const bool timing = (q.opts.flags & HS_FLAG_TIMING) != 0;
     const bool graph = !timing && (q.opts.flags & HS_FLAG_GRAPH) && st != nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // ev[0..3]: stage times; ev[4]: the end of a pass's front part (shared)
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     if (timing)
-        for (auto& e : ev) HS_HIP(hipEventCreate(&e), "hipEventCreate");
+        for (int i = 0; i < 4; ++i) HS_HIP(hipEventCreate(&ev[i]), "hipEventCreate");
+    if (shared && !graph && !timing)
+        HS_HIP(hipEventCreateWithFlags(&ev[4], hipEventDisableTiming), "hipEventCreate");
     struct EvGuard {
         hipEvent_t* e;
         ~EvGuard()
         {
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 5; ++i)
                 if (e[i]) (void)hipEventDestroy(e[i]);
         }
     } guard{ev};
@@ -434,11 +461,22 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
             L.ca.timeout_ticks = wall_clock_ticks(10.0);
         }
         std::unique_lock<std::mutex> cluster_lock(g_cluster_mu, std::defer_lock);
-        if (L.cluster) cluster_lock.lock();
-        if (graph)
+        if (graph) {
+            if (L.cluster) cluster_lock.lock();
             HS_HIP(launch_pass_graph(L, ws, st), "graph launch");
-        else
+        } else if (ev[4] && L.cluster && L.window == 0) {
+            // shared device (the server): the path and Gram kernels run beside
+            // other requests' work; only the cluster sweep, whose workgroups
+            // must all be resident at once, waits for the device to itself
+            HS_HIP(enqueue_front(L, st, nullptr), "kernel launch");
+            HS_HIP(hipEventRecord(ev[4], st), "hipEventRecord");
+            HS_HIP(hipEventSynchronize(ev[4]), "hipEventSynchronize");
+            cluster_lock.lock();
+            HS_HIP(enqueue_back(L, st, nullptr), "kernel launch");
+        } else {
+            if (L.cluster) cluster_lock.lock();
             HS_HIP(enqueue_pass(L, st, timing ? ev : nullptr), "kernel launch");
+        }
 
         // results [Sp][4] and the status flag right after them: one copy
         std::vector<double> out(static_cast<size_t>(Sp) * 4 + 1);
@@ -601,7 +639,8 @@ hs_status hs_autotune(const hs_model* model, const double* corr, const hs_option
     if (rc != HS_OK) return rc;
     rc = validate(q);
     if (rc != HS_OK) return rc;
-    q.opts.flags &= ~(HS_FLAG_TIMING | HS_FLAG_EXPORT_TAU | HS_FLAG_GRAPH);
+    // candidates run as the request will: graph replay stays on if asked for
+    q.opts.flags &= ~(HS_FLAG_TIMING | HS_FLAG_EXPORT_TAU);
     q.opts.waves_per_block = 0;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     // target waves (the default first) x the most waves per block (1: as

@@ -30,8 +30,11 @@ void store_tuned_shape(const Request& q, const Tune& t);
 
 // Enqueues and completes (synchronizes st) the whole Greek set of a validated
 // request in the given workspace; tune == nullptr uses the tuned table.
+// shared: other streams of this process run Greek sets on the device at the
+// same time (the server); each pass then holds the device to itself only for
+// its cluster sweep, not for its path and Gram kernels.
 hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream_t st,
-                        RunResult& res, const Tune* tune);
+                        RunResult& res, const Tune* tune, bool shared = false);
 void fill_greeks(const Request& q, const RunResult& res, hs_greeks* out);
 size_t workspace_bound(const Request& q, bool minimum);
 int default_target_waves();

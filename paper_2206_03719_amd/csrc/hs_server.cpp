@@ -1,15 +1,23 @@
 // hs_server.cpp -- continuous-batching request loop.
 //
 // The server owns a caller-provided device pool (the HBM budget).  Requests
-// queue in arrival order; the head of the queue is admitted as soon as a slot
-// is idle and the pool has room for its workspace, so requests that arrive
-// while others run start as slots and memory free up.  Every slot is a host
-// worker thread with its own HIP stream (default priority); admitted requests
-// therefore overlap on the device.  A request's plan depends only on the
-// request and the pool size, and every kernel reduction has a fixed order, so
-// its results are bit-identical alone and in any mix.
+// queue in arrival order; an idle slot admits the first queued request whose
+// workspace fits the free pool (first fit), so a small request may pass a
+// large one that is waiting for memory -- but a request at the head of the
+// queue is passed at most 2 x slots times, after which the slots wait for it.
+// Requests that arrive while others run start as slots and memory free up.
+// Every slot is a host worker thread with its own HIP stream (default
+// priority).  The path and Gram kernels of admitted requests run side by side
+// on the device; a backward sweep whose workgroups wait on each other (the
+// cluster sweep) runs while no other such sweep does, so that all its
+// workgroups can be resident.  Each request's device interval (HIP events on
+// its stream against one reference event) is kept, and the statistics report
+// how many requests were on the device at once.  A request's plan depends
+// only on the request, and every kernel reduction has a fixed order, so its
+// results are bit-identical alone and in any mix.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -18,6 +26,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/hs_api.h"
@@ -88,6 +97,12 @@ struct Item {
     std::string error;
     RunResult res;
     Clock::time_point t_submit, t_done;
+    int passed = 0;  // admissions of later requests while this one was queued
+};
+
+// Times (seconds) a request's work was on the device, from the reference event.
+struct Interval {
+    double start, end;
 };
 
 }  // namespace
@@ -106,39 +121,71 @@ struct hs_server {
     bool stop = false;
     int64_t submitted = 0, completed = 0, cancelled = 0, failed = 0, running = 0;
     double path_steps = 0.0;
+    int max_slots = 1;
+    hipEvent_t ref = nullptr;  // device-time origin of the request intervals
+    std::vector<hs::Interval> intervals;
     static constexpr size_t kQueueCap = 4096;
 };
 
 namespace hs {
 namespace {
 
+// First fit over the queue (caller holds s->mu): the first queued request
+// whose workspace the free pool holds, reserving it at *off.  The head may be
+// passed at most 2 x slots times; after that only the head is admitted.
+std::deque<Item*>::iterator admit(hs_server* s, size_t* off)
+{
+    auto& q = s->queue;
+    for (auto it = q.begin(); it != q.end(); ++it) {
+        if (s->alloc.alloc((*it)->ws, off)) {
+            if (it != q.begin()) ++q.front()->passed;
+            return it;
+        }
+        if (it == q.begin() && (*it)->passed >= 2 * s->max_slots) break;
+    }
+    return q.end();
+}
+
 void worker_main(hs_server* s)
 {
     (void)hipSetDevice(s->device);
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+        (void)hipStreamDestroy(st);
+        st = nullptr;
+    }
     for (;;) {
         Item* it = nullptr;
         size_t off = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
+            std::deque<Item*>::iterator pick;
             s->cv.wait(lk, [&] {
                 if (s->stop) return true;
-                if (s->queue.empty()) return false;
-                return s->alloc.alloc(s->queue.front()->ws, &off);
+                pick = admit(s, &off);
+                return pick != s->queue.end();
             });
             if (s->stop) break;
-            it = s->queue.front();
-            s->queue.pop_front();
+            it = *pick;
+            s->queue.erase(pick);
             it->state = St::Running;
             ++s->running;
         }
         RunResult res;
         hs_status rc = HS_EDEVICE;
         std::string err;
+        Interval iv{0.0, 0.0};
         if (st) {
-            rc = run_greek_set(it->q, s->pool + off, it->ws, st, res, nullptr);
+            (void)hipEventRecord(e0, st);
+            rc = run_greek_set(it->q, s->pool + off, it->ws, st, res, nullptr, true);
             if (rc != HS_OK) err = hs_last_error();
+            float a = 0.f, b = 0.f;
+            if (hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                hipEventElapsedTime(&a, s->ref, e0) == hipSuccess &&
+                hipEventElapsedTime(&b, s->ref, e1) == hipSuccess)
+                iv = Interval{a * 1e-3, b * 1e-3};
         } else {
             err = "could not create a HIP stream for this slot";
         }
@@ -155,13 +202,39 @@ void worker_main(hs_server* s)
                 ++s->completed;
                 s->path_steps += static_cast<double>(it->res.price.size()) *
                                  static_cast<double>(it->q.P) * it->q.n;
+                if (iv.end > iv.start) s->intervals.push_back(iv);
             } else {
                 ++s->failed;
             }
         }
         s->cv.notify_all();
     }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (st) (void)hipStreamDestroy(st);
+}
+
+// The most requests on the device at once, and the seconds during which at
+// least two were, over the completed requests' device intervals.
+void overlap_of(const std::vector<Interval>& iv, int* most, double* overlap_s)
+{
+    std::vector<std::pair<double, int>> ev;
+    ev.reserve(iv.size() * 2);
+    for (const Interval& i : iv) {
+        ev.emplace_back(i.start, +1);
+        ev.emplace_back(i.end, -1);
+    }
+    std::sort(ev.begin(), ev.end());  // an end before a start at equal times
+    int cur = 0, hi = 0;
+    double t_prev = 0.0, both = 0.0;
+    for (const auto& e : ev) {
+        if (cur >= 2) both += e.first - t_prev;
+        cur += e.second;
+        hi = std::max(hi, cur);
+        t_prev = e.first;
+    }
+    *most = hi;
+    *overlap_s = both;
 }
 
 }  // namespace
@@ -188,6 +261,18 @@ hs_status hs_server_create(int device, void* d_pool, size_t pool_bytes, int32_t 
     s->device = device;
     s->pool = static_cast<unsigned char*>(d_pool);
     s->alloc = PoolAlloc(pool_bytes);
+    s->max_slots = max_slots;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess ||
+        hipEventCreate(&s->ref) != hipSuccess || hipEventRecord(s->ref, nullptr) != hipSuccess ||
+        hipEventSynchronize(s->ref) != hipSuccess) {
+        set_error("hs_server_create: could not record the reference event");
+        if (s->ref) (void)hipEventDestroy(s->ref);
+        (void)hipSetDevice(prev);
+        delete s;
+        return HS_EDEVICE;
+    }
+    (void)hipSetDevice(prev);
     for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker_main, s);
     *out = s;
     return HS_OK;
@@ -217,7 +302,10 @@ hs_status hs_submit(hs_server* s, const hs_request* r, uint64_t* ticket)
         set_error("hs_submit: request needs at least %zu bytes, the pool has %zu", mn, cap);
         return HS_ENOMEM;
     }
-    it->ws = full <= cap ? full : cap;
+    // a request larger than the pool runs in passes in half of it (or its
+    // minimum), so that it leaves room for others; results do not depend on
+    // the workspace size
+    it->ws = full <= cap ? full : std::max(mn, cap / 2);
     it->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -319,6 +407,12 @@ hs_status hs_server_get_stats(hs_server* s, hs_server_stats* out)
     out->pool_in_use = s->alloc.used();
     out->pool_peak = s->alloc.peak();
     out->path_steps_done = s->path_steps;
+    int most = 0;
+    double both = 0.0;
+    overlap_of(s->intervals, &most, &both);
+    out->device_max_concurrent = most;
+    out->device_overlap_s = both;
+    out->slots = s->max_slots;
     return HS_OK;
 }
 
@@ -336,6 +430,7 @@ void hs_server_destroy(hs_server* s)
     }
     s->cv.notify_all();
     for (auto& t : s->workers) t.join();
+    if (s->ref) (void)hipEventDestroy(s->ref);
     delete s;
 }
 

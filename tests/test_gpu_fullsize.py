@@ -101,7 +101,7 @@ def test_ten_assets_200k_greek_set():
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.Stream()
     hs.autotune(w["model"], w["corr"], w["option"], w["n_paths"], 252, w["bumps"], seed=w["seed"],
-                workspace=ws, stream=stream, repeats=1)
+                workspace=ws, stream=stream, repeats=1, graph=True)
     g = hs.price_greeks(w["model"], w["corr"], w["option"], w["n_paths"], 252, w["bumps"],
                         seed=w["seed"], precision="fp32", workspace=ws, stream=stream, graph=True)
     del ws

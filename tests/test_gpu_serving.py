@@ -1,5 +1,6 @@
-"""Serving loop on the GPU: continuous batching by HBM budget, overlap of
-requests in flight, and each request's result bit-identical alone and in a
+"""Serving loop on the GPU: continuous batching by HBM budget with first-fit
+admission, overlap of requests on the device (their device intervals from HIP
+events intersect), and each request's result bit-identical alone and in a
 mix of uneven requests."""
 import sys
 import time
@@ -104,9 +105,44 @@ def test_budget_admission_and_overlap():
         time.sleep(0.0005)
     st = srv.stats()
     srv.close()
+    _say("  device: at most %d requests at once, %.4f s with two or more"
+         % (st["device_max_concurrent"], st["device_overlap_s"]))
     assert st["completed"] == len(reqs)
     assert st["pool_peak"] <= pool
-    assert seen_running >= 2  # requests overlapped on the device
+    assert seen_running >= 2
+    # overlap on the device itself: the requests' device intervals (HIP
+    # events on their streams) intersect
+    assert st["device_max_concurrent"] >= 2
+    assert st["device_overlap_s"] > 0.0
+
+
+def test_first_fit_admission_passes_a_waiting_request():
+    # A takes most of the pool; B (as large) waits at the head of the queue;
+    # C (small) fits beside A and is admitted past B, so it finishes first
+    import paper_2206_03719_amd as hs
+    big = W.best_of_call(n_assets=6, n_paths=60000, n_steps=126)
+    small = W.best_of_call(n_assets=2, n_paths=4000, n_steps=26)
+    nb = hs.workspace_bytes(big["model"], big["option"], 60000, 126, big["bumps"])
+    ns = hs.workspace_bytes(small["model"], small["option"], 4000, 26, small["bumps"])
+    assert ns * 4 < nb
+    srv = hs.Server(nb + 2 * ns, max_slots=4)
+    ta = srv.submit(big)
+    time.sleep(0.05)
+    tb = srv.submit(big)
+    tc = srv.submit(small)
+    order = []
+    t0 = time.time()
+    pending = {ta, tb, tc}
+    while pending:
+        for t in list(pending):
+            if srv.poll(t) is not None:
+                order.append(t)
+                pending.discard(t)
+        assert time.time() - t0 < 120
+        time.sleep(0.0005)
+    srv.close()
+    _say("  completion order: %s (a=%d b=%d c=%d)" % (order, ta, tb, tc))
+    assert order.index(tc) < order.index(tb)
 
 
 def test_request_over_budget_runs_in_passes():
