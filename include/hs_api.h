@@ -259,6 +259,25 @@ hs_status hs_price_greeks(const hs_model *model, const double *corr, const hs_op
                           const hs_opts *opts, void *d_workspace, size_t workspace_bytes,
                           void *hip_stream, hs_greeks *out);
 
+/* hs_price_greeks without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same Greek set, with the same arguments, errors and
+ * results (bit for bit), run in a workspace the library holds itself -- a
+ * static device array of HS_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends.  A request whose minimum workspace (hs_workspace_min_bytes)
+ * exceeds it is rejected with HS_ENOMEM before any device work; smaller ones
+ * run in passes and windows of dates where they do not fit at once.  The
+ * call allocates no device memory (HS_FLAG_GRAPH and HS_FLAG_TIMING, which
+ * create runtime objects, are rejected with HS_EINVAL).  Every call on a GPU
+ * uses that GPU's one array, and each pass rewrites what it reads (tables,
+ * status flags, exchange slots): calls that overlap on one GPU race and must
+ * not be made. */
+#define HS_NOALLOC_SCRATCH_BYTES (64u << 20)
+hs_status hs_price_greeks_noalloc(const hs_model *model, const double *corr,
+                                  const hs_option *option, int64_t n_paths, int32_t n_steps,
+                                  const hs_bumps *bumps, const hs_opts *opts, void *hip_stream,
+                                  hs_greeks *out);
+
 /* The paper's measured kernel on its own (Sec. 2.2.1 and 4.1, the problem
  * sizes of its Table 1): Heston paths of the base model and, at each date
  * k = 1..n_steps, the path reduction U = max_i S_i and A = (1/N) sum_i

@@ -23,6 +23,7 @@ BUMP_DELTA_GAMMA, BUMP_VEGA, BUMP_THETA, BUMP_RHO, BUMP_CORR, BUMP_ALL = 1, 2, 4
 FP64, FP32_PATHS = 0, 1
 FLAG_EXPORT_TAU, FLAG_TIMING, FLAG_GRAPH, FLAG_GREEK_SET_KERNEL = 1, 2, 4, 8
 MAX_ASSETS, MAX_PATH_ASSETS = 20, 64
+NOALLOC_SCRATCH_BYTES = 64 << 20  # HS_NOALLOC_SCRATCH_BYTES
 SCHEME_EULER_FT, SCHEME_QE = 0, 1
 SCHEMES = {"euler": SCHEME_EULER_FT, "qe": SCHEME_QE}
 FEATURES_NATIVE, FEATURES_FP16, FEATURES_BF16 = 0, 1, 2
@@ -111,6 +112,11 @@ _SIGS = {
                                          ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Bumps),
                                          ctypes.POINTER(Opts), ctypes.c_void_p, ctypes.c_size_t,
                                          ctypes.c_void_p, ctypes.POINTER(Greeks)]),
+    "hs_price_greeks_noalloc": (ctypes.c_int32, [ctypes.POINTER(Model), _dp,
+                                                 ctypes.POINTER(Option), ctypes.c_int64,
+                                                 ctypes.c_int32, ctypes.POINTER(Bumps),
+                                                 ctypes.POINTER(Opts), ctypes.c_void_p,
+                                                 ctypes.POINTER(Greeks)]),
     "hs_autotune": (ctypes.c_int32, [ctypes.POINTER(Model), _dp, ctypes.POINTER(Option),
                                      ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Bumps),
                                      ctypes.POINTER(Opts), ctypes.c_void_p, ctypes.c_size_t,
@@ -230,21 +236,22 @@ def _stream_handle(stream):
 def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precision="fp32",
                  workspace=None, stream=None, export_tau=False, timing=False,
                  waves_per_block=0, sweep_mode=0, graph=False, scheme="euler",
-                 features="native", window_dates=0):
+                 features="native", window_dates=0, noalloc=False):
     """Price + bump-and-revalue Greeks of one option (hs_price_greeks).
 
     ``workspace``: a CUDA uint8 tensor (allocated here when None).  ``graph``:
     replay the pass's kernels from a cached HIP graph.  ``window_dates``: run
     the backward sweep in windows of that many dates with checkpoint-recompute
-    of the paths (0: only if the workspace needs it).  Returns a dict of numpy
-    arrays / floats."""
+    of the paths (0: only if the workspace needs it).  ``noalloc``: call
+    hs_price_greeks_noalloc instead, which runs in the library's static
+    scratch (no workspace).  Returns a dict of numpy arrays / floats."""
     torch = _torch()
     flags = ((FLAG_EXPORT_TAU if export_tau else 0) | (FLAG_TIMING if timing else 0) |
              (FLAG_GRAPH if graph else 0))
     m = _Marshal(model, corr, option, bumps, seed, precision, flags, waves_per_block, sweep_mode,
                  scheme, features, window_dates)
     N = m.N
-    if workspace is None:
+    if workspace is None and not noalloc:
         nbytes = workspace_bytes(model, option, n_paths, n_steps, bumps, precision, flags=flags,
                                  sweep_mode=sweep_mode, scheme=scheme, features=features,
                                  window_dates=window_dates)
@@ -259,11 +266,17 @@ def price_greeks(model, corr, option, n_paths, n_steps, bumps, seed=42, precisio
         setattr(g, k, a.ctypes.data_as(_dp))
     if tau is not None:
         g.tau = tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-    st = lib().hs_price_greeks(ctypes.byref(m.model), m.corr_ptr, ctypes.byref(m.option),
-                               int(n_paths), int(n_steps), ctypes.byref(m.bumps),
-                               ctypes.byref(m.opts), ctypes.c_void_p(workspace.data_ptr()),
-                               workspace.numel() * workspace.element_size(),
-                               _stream_handle(stream), ctypes.byref(g))
+    if noalloc:
+        st = lib().hs_price_greeks_noalloc(ctypes.byref(m.model), m.corr_ptr,
+                                           ctypes.byref(m.option), int(n_paths), int(n_steps),
+                                           ctypes.byref(m.bumps), ctypes.byref(m.opts),
+                                           _stream_handle(stream), ctypes.byref(g))
+    else:
+        st = lib().hs_price_greeks(ctypes.byref(m.model), m.corr_ptr, ctypes.byref(m.option),
+                                   int(n_paths), int(n_steps), ctypes.byref(m.bumps),
+                                   ctypes.byref(m.opts), ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel() * workspace.element_size(),
+                                   _stream_handle(stream), ctypes.byref(g))
     _check(st)
     res = {"price": g.price, "price_se": g.price_se, "theta": g.theta, "rho": g.rho,
            "n_scenarios": g.n_scenarios, "skipped_regressions": g.skipped_regressions,

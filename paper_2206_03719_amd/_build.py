@@ -33,6 +33,7 @@ SOURCES = [
     ("hs_lsmc.hip", HIP_FLAGS),
     ("hs_paths_base.hip", HIP_FLAGS),
     ("hs_kernels.hip", HIP_FLAGS),
+    ("hs_noalloc.hip", HIP_FLAGS),
     ("hs_plan.cpp", HOST_FLAGS),
     ("hs_api.cpp", HOST_FLAGS),
     ("hs_server.cpp", HOST_FLAGS),
