@@ -104,7 +104,7 @@ void append_bytes(std::string& k, const T& v)
 
 // Everything one pass enqueues after its tables are uploaded.
 struct PassLaunch {
-    bool fp32 = true, american = true, cluster = false, keep = false;
+    bool fp32 = true, american = true, cluster = false;
     int scheme = HS_SCHEME_EULER_FT;
     int feat = kFeatF32;
     int nmax = 0, nchunks = 0, nbg = 0, Sp = 0, cluster_q = 0, per_launch = 0, sweep_q = 0;
@@ -123,7 +123,7 @@ hipError_t enqueue_sweep(const PassLaunch& L, const LsmcArgs& la, hipStream_t st
         ClusterArgs ca = L.ca;
         for (int s0 = 0; s0 < L.Sp; s0 += L.per_launch) {
             ca.s0 = s0;
-            if ((e = launch_sweep_cluster(L.feat, L.cluster_q, L.keep, la, ca,
+            if ((e = launch_sweep_cluster(L.feat, L.cluster_q, la, ca,
                                           std::min(L.per_launch, L.Sp - s0), st)) != hipSuccess)
                 return e;
         }
@@ -233,7 +233,6 @@ hipError_t launch_pass_graph(const PassLaunch& L, void* ws, hipStream_t st)
     append_bytes(key, L.fp32);
     append_bytes(key, L.american);
     append_bytes(key, L.cluster);
-    append_bytes(key, L.keep);
     append_bytes(key, L.nmax);
     append_bytes(key, L.scheme);
     append_bytes(key, L.feat);
@@ -433,11 +432,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         L.cluster = sh.sweep == kSweepCluster;
         int cap = 0;
         if (L.cluster) {
-            // a Greek set that one workgroup per CU holds keeps the basis values
-            // in registers; a larger one fits two workgroups per CU without
-            // (windows run the variant without kept values)
-            L.keep = L.window == 0 && static_cast<int64_t>(Sp) * sh.cluster_g <= kPlanComputeUnits;
-            cap = cluster_capacity(sh.feat, sh.cluster_q, L.keep, L.window > 0,
+            cap = cluster_capacity(sh.feat, sh.cluster_q, L.window > 0,
                                    cluster_lds_bytes(q.n, sh.cluster_g));
             if (cap < sh.cluster_g) {
                 if (q.opts.sweep_mode == 3) {

@@ -117,6 +117,29 @@ __device__ __forceinline__ cptr<T> as_const(const void* p)
     return reinterpret_cast<cptr<T>>(reinterpret_cast<uintptr_t>(p));
 }
 
+// Raw buffer access to `bytes` bytes from p: a load whose lane offset (voff)
+// is at or past the end reads 0 (the buffer unit's range check covers the
+// lane offset, so callers put the whole offset there and pass soff = 0), and
+// a ragged last chunk of paths needs no clamped addresses.  Descriptor word
+// 3, 0x00020000, is the raw (unformatted) buffer of the GFX9 family's
+// resource layout.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_over(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes),
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "buffer_load size");
+    if constexpr (sizeof(T) == 16)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    else if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // Uniform (wave-wide) select of arr[i] as a chain of selects with constant
 // indices (instantiated per index, so the array stays in registers).
 template <int J, typename R, int NM>

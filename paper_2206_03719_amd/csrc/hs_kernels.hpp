@@ -45,16 +45,15 @@ hipError_t launch_gram(int feat, const LsmcArgs& a, int S, hipStream_t st);
 int sweep_q_for(int64_t P);
 hipError_t launch_sweep(int feat, int q, const LsmcArgs& a, int S, hipStream_t st);
 
-// Cluster sweep: Q in 1..8 paths per thread, G workgroups per scenario,
-// S_launch scenarios (planes c.s0 ..) per launch; keep = each path keeps its
-// basis values between a date's regression and its decision (more registers);
-// capacity = workgroups that fit on the device at once.  A launch over a
-// window of dates (LsmcArgs k_lo, k_hi, win_first, win_last not the whole
-// sweep) runs a variant of its own, without kept basis values.
+// Cluster sweep: Q paths per thread (cluster_q_supported), G workgroups per
+// scenario, S_launch scenarios (planes c.s0 ..) per launch; capacity =
+// workgroups that fit on the device at once.  A launch over a window of
+// dates (LsmcArgs k_lo, k_hi, win_first, win_last not the whole sweep) runs a
+// variant of its own.
 size_t cluster_lds_bytes(int n, int G);
-int cluster_capacity(int feat, int q, bool keep, bool win, size_t lds);
-hipError_t launch_sweep_cluster(int feat, int q, bool keep, const LsmcArgs& a,
-                                const ClusterArgs& c, int S_launch, hipStream_t st);
+int cluster_capacity(int feat, int q, bool win, size_t lds);
+hipError_t launch_sweep_cluster(int feat, int q, const LsmcArgs& a, const ClusterArgs& c,
+                                int S_launch, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, int64_t count, uint64_t value, hipStream_t st);
 
 hipError_t launch_philox_words(uint64_t seed, int64_t P, int n, int nb, uint32_t* out,

@@ -199,9 +199,18 @@ constexpr int kClusterThreads = 512;
 constexpr int kPartStride = 8;  // doubles per published workgroup partial
 constexpr int kMaxClusterGroups = 1024;
 constexpr int kPlanComputeUnits = 256;  // MI355X: the cluster sweep plans for this many CUs
-// Most paths per thread with which a workgroup of the cluster sweep that does
-// not keep basis values fits 128 registers (two workgroups per CU).
-constexpr int cluster_qmax_shared(bool fp32) { return fp32 ? 6 : 4; }
+// Paths per thread of the cluster sweep: the counts it is compiled for, and
+// the most a workgroup holds in registers (two dates of features and the
+// discounted cash flow per path, with the compiler's temporaries about 11
+// registers per path with 8-byte features, FP32 pairs, and 15 with FP64
+// pairs; up to 6 paths per thread two workgroups share a CU, above that one
+// workgroup per CU with up to 256 registers, which holds 16 (FP64 pairs: 12)
+// without spilling; 16-bit pairs spill at 16).
+constexpr bool cluster_q_supported(int q, int ft)
+{
+    return (q >= 1 && q <= 8) || q == 10 || q == 12 || (ft == kFeatF32 && q == 16);
+}
+constexpr int cluster_qmax(int ft) { return ft == kFeatF32 ? 16 : 12; }
 
 // Partial slots start as kEmptySlot (a NaN bit pattern that arithmetic never
 // produces); a workgroup's published partial is the slot's only write.

@@ -566,16 +566,21 @@ __device__ __forceinline__ bool cluster_exchange(double (&b)[K], int m, double* 
     return true;
 }
 
-// KEEP: each path keeps the payoff and centred basis variables of the date it
-// last entered the regression, so that date's exercise decision needs no
-// recomputation (more registers: one workgroup per CU).  Otherwise the
-// decision recomputes them from that date's features, within 128 registers so
-// that two workgroups share a CU (4 waves per SIMD), for Greek sets larger
-// than one workgroup per CU can hold.  Both give the same numbers.
-template <typename R, int Q, bool KEEP, bool WIN>
-__global__ void __launch_bounds__(kClusterThreads,
-                                  (!KEEP && !WIN && Q <= cluster_qmax_shared(sizeof(R) <= 4)) ? 4
-                                                                                             : 2)
+// Each thread holds the Q paths pbase + i 512 + t (i < Q, pbase = g 512 Q) of
+// its workgroup g: their discounted cash flows and two dates of features, in
+// registers.  At date k the buffer `cur` holds date k's features and `old`
+// date k + 1's: the exercise decision of date k + 1 (its regression solved
+// one exchange ago) reads `old`, which then receives date k - 1's loads; the
+// right-hand side of date k reads `cur`.  The loads are issued before date
+// k's exchange, so they fly during it (the exchange's polls complete after
+// them: vector loads of a wave complete in order), and nothing waits for them
+// until date k - 1.  The loop is unrolled twice so that the two buffers swap
+// roles by renaming.  Up to 6 paths per thread two workgroups share a CU
+// (4 waves per SIMD, 128 registers); more paths per thread (large Greek sets:
+// fewer launches, each a chain of exchanges) take one workgroup per CU and up
+// to 256 registers.
+template <typename R, int Q, bool WIN>
+__global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
     k_sweep_cluster(const LsmcArgs A, const ClusterArgs C)
 {
     extern __shared__ unsigned char hs_smem[];
@@ -591,8 +596,8 @@ __global__ void __launch_bounds__(kClusterThreads,
     const int s = C.s0 + sl;
     const int64_t P = A.P;
     const int m = A.m;
-    const R2<R>* __restrict__ F = static_cast<const R2<R>*>(A.feat) + s * A.plane;
-    if (threadIdx.x == 0) *Ls.flag = 1;
+    const int tid = threadIdx.x;
+    if (tid == 0) *Ls.flag = 1;
     __syncthreads();
 
     const int64_t row_len = static_cast<int64_t>(G) * kPartStride;
@@ -603,7 +608,12 @@ __global__ void __launch_bounds__(kClusterThreads,
     const cptr<RegRec> recs = as_const<RegRec>(A.reg) + static_cast<int64_t>(s) * n;
     const cptr<double> dsc = as_const<double>(A.disc) + static_cast<int64_t>(s) * (n + 1);
     const cptr<double> idsc = as_const<double>(A.idisc) + static_cast<int64_t>(s) * (n + 1);
-    const int64_t pbase = static_cast<int64_t>(g) * (kClusterThreads * Q) + threadIdx.x;
+    // this workgroup's chunk of paths [pbase, pbase + chunk) of scenario s
+    const int64_t pbase = static_cast<int64_t>(g) * (kClusterThreads * Q);
+    const int chunk = static_cast<int>(min<int64_t>(static_cast<int64_t>(kClusterThreads) * Q,
+                                                    P - pbase));
+    const int nlive = chunk > tid ? (chunk - tid + kClusterThreads - 1) / kClusterThreads : 0;
+    const R2<R>* __restrict__ const F = static_cast<const R2<R>*>(A.feat) + s * A.plane + pbase;
     // a window of dates (WIN), else every date: regressions k_top..k_lo, the
     // features of date d at index d - f0
     const int f0 = WIN ? A.f_date0 : 1;
@@ -613,30 +623,41 @@ __global__ void __launch_bounds__(kClusterThreads,
     const int k_top = WIN ? min(A.k_hi, n - 1) : n - 1;
     int par = 0;
 
+    // Q loads of one date into buf, through a buffer resource over this
+    // chunk's paths of that date: the whole offset is in the lane's offset,
+    // which the buffer unit range-checks, so paths past the chunk read 0
+    // (never used) instead of memory past the plane
+    const uint32_t voff = static_cast<uint32_t>(tid) * sizeof(R2<R>);
+    auto load = [&](int k, R2<R>(&buf)[Q]) {
+        const auto rs = buffer_over(F + static_cast<int64_t>(k - f0) * P,
+                                    static_cast<uint32_t>(chunk) * sizeof(R2<R>));
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            buf[i] = buffer_load<R2<R>>(rs, voff + i * kClusterThreads * sizeof(R2<R>), 0);
+    };
+
     // State per path: the cash flow discounted to time 0, D = h_tau exp(-r tau
     // dt).  The regression target at date k is D exp(r k dt) =
     // h_tau exp(-r (tau - k) dt), and the price is the mean of D.  The exercise
     // date tau, wanted only for export, goes straight to memory at each
     // exercise (the sweep runs backward, so the last write is the earliest
     // exercise date).
-    // Path pbase + i kClusterThreads exists iff i < nlive (the last workgroup
-    // of a scenario may be ragged).
-    const int64_t room = P - pbase;
-    const int nlive = room <= 0 ? 0 : (room + kClusterThreads - 1) / kClusterThreads;
-    int32_t* const tau = A.export_tau ? A.tau + static_cast<int64_t>(s) * P + pbase : nullptr;
-    // (a window after the first takes D from the workspace, where the
-    // previous window left it)
+    int32_t* const tau = A.export_tau ? A.tau + static_cast<int64_t>(s) * P + pbase + tid : nullptr;
     double D[Q];
     if (!WIN || A.win_first) {
+        R2<R> fn[Q];
+        const auto rs = buffer_over(F + last, static_cast<uint32_t>(chunk) * sizeof(R2<R>));
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            fn[i] = buffer_load<R2<R>>(rs, voff + i * kClusterThreads * sizeof(R2<R>), 0);
         const double dn = dsc[n];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const int64_t p = pbase + i * kClusterThreads;
-            D[i] = i < nlive ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) * dn : 0.0;
+            D[i] = i < nlive ? payoff(A.cp, A.K, static_cast<double>(fn[i].u)) * dn : 0.0;
             if (tau && i < nlive) tau[i * kClusterThreads] = n;
         }
     } else {
-        const double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase;
+        const double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase + tid;
 #pragma unroll
         for (int i = 0; i < Q; ++i) D[i] = i < nlive ? dstate[i * kClusterThreads] : 0.0;
     }
@@ -645,78 +666,38 @@ __global__ void __launch_bounds__(kClusterThreads,
     bool have = false;  // beta of the later date k+1 is valid
     double skipped = 0.0;
     if (A.american) {
-        // Three feature buffers take turns: at date k, cur holds date k (this
-        // regression), nxt date k-1 (loaded one date ago) and old date k+1
-        // (without KEEP, its decision's features); after the exchange old
-        // receives date k-2.  The loop is unrolled three times so the roles
-        // rotate by renaming and a load's destination is not read until two
-        // dates later: the loads fly across the next date's work.
-        R bu[3][Q], ba[3][Q];
-        // payoff and centred basis variables of each path at the date last
-        // regressed, kept for that date's exercise decision (h = 0: out of
-        // the money, no decision)
-        double hh[Q], xx[Q], ww[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int64_t p = pbase + i * kClusterThreads;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                bu[j][i] = R(0);
-                ba[j][i] = R(0);
-            }
-            hh[i] = 0.0;
-            xx[i] = 0.0;
-            ww[i] = 0.0;
-            if (i < nlive && k_top >= k_lo) {
-                const R2<R> f = F[static_cast<int64_t>(k_top - f0) * P + p];
-                bu[0][i] = f.u;
-                ba[0][i] = f.a;
-            }
-            if (i < nlive && k_top - 1 >= k_lo) {
-                const R2<R> f = F[static_cast<int64_t>(k_top - 1 - f0) * P + p];
-                bu[1][i] = f.u;
-                ba[1][i] = f.a;
-            }
-        }
+        R2<R> fa[Q], fb[Q];
+        if (k_top >= k_lo) load(k_top, fa);
         // regression-set flag and means of date k, loaded one date ahead
         double r_ok = k_top >= k_lo ? recs[k_top - 1].ok : 0.0;
         double r_cU = k_top >= k_lo ? recs[k_top - 1].cU : 0.0;
         double r_cA = k_top >= k_lo ? recs[k_top - 1].cA : 0.0;
         double bcU = 0.0, bcA = 0.0;  // regression-set means of date k+1
 
-        // the exercise decision at date kd with the regression of that date
-        // (beta, bcU, bcA), from the kept values or from that date's features
-        auto decide = [&](int kd, const R (&du)[Q], const R (&da)[Q]) {
+        // the exercise decision at date kd with that date's regression (beta,
+        // bcU, bcA) and features.  The basis values are recomputed from the
+        // features: an empty asm statement hides that they equal the ones the
+        // right-hand side formed one exchange earlier, so that the compiler
+        // does not keep those (4 more registers per path) across the exchange.
+        auto decide = [&](int kd, R2<R>(&f)[Q]) {
             const double d1 = dsc[kd];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                double h, x, w;
-                if constexpr (KEEP) {
-                    h = hh[i];
-                    x = xx[i];
-                    w = ww[i];
-                } else {
-                    const double U = static_cast<double>(du[i]);
-                    h = i < nlive ? payoff(A.cp, A.K, U) : 0.0;
-                    double phi[5];
-                    basis(m, U, static_cast<double>(da[i]), bcU, bcA, A.inv_K, A.inv_tbar, phi);
-                    x = phi[1];
-                    w = phi[3];
-                }
-                if (h > 0.0) {
-                    const double cont = beta[0] + beta[1] * x + beta[2] * (x * x) + beta[3] * w +
-                                        beta[4] * (x * w);
-                    if (h > cont) {
-                        D[i] = h * d1;
-                        if (tau) tau[i * kClusterThreads] = kd;
-                    }
-                }
+                asm volatile("" : "+v"(f[i].u), "+v"(f[i].a));
+                const double U = static_cast<double>(f[i].u);
+                const double h = payoff(A.cp, A.K, U);
+                const double x = (U - bcU) * A.inv_K;
+                const double w = m == 5 ? (static_cast<double>(f[i].a) - bcA) * A.inv_tbar : 0.0;
+                const double cont = beta[0] + beta[1] * x + beta[2] * (x * x) + beta[3] * w +
+                                    beta[4] * (x * w);
+                const bool ex = i < nlive && h > 0.0 && h > cont;
+                D[i] = ex ? h * d1 : D[i];
+                if (tau && ex) tau[i * kClusterThreads] = kd;
             }
         };
 
-        // one date k with buffers cur = C, old = O; false if a wait timed out
-        auto step = [&](int k, auto Ci, auto Oi) -> bool {
-            constexpr int CB = decltype(Ci)::value, OB = decltype(Oi)::value;
+        // one date k (cur: date k, old: date k + 1); false if a wait timed out
+        auto step = [&](int k, R2<R>(&cur)[Q], R2<R>(&old)[Q]) -> bool {
             const bool ok = r_ok != 0.0;
             const double cU = r_cU, cA = r_cA;
             if (k > k_lo) {
@@ -724,34 +705,31 @@ __global__ void __launch_bounds__(kClusterThreads,
                 r_cU = recs[k - 2].cU;
                 r_cA = recs[k - 2].cA;
             }
-            const double ik = idsc[k];
-            // exercise at date k+1 with its regression, then this date's
-            // right-hand side with the updated cash flows
-            if (have) decide(k + 1, bu[OB], ba[OB]);
+            // exercise at date k+1 with its regression, then the next date's
+            // loads into its buffer, then this date's right-hand side with the
+            // updated cash flows
+            if (have) decide(k + 1, old);
+            if (k - 1 >= k_lo) load(k - 1, old);
             double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                if constexpr (KEEP) hh[i] = 0.0;
-                if (ok) {
-                    const double U = static_cast<double>(bu[CB][i]);
-                    const double h = payoff(A.cp, A.K, U);
-                    if (i < nlive && h > 0.0) {
-                        double phi[5];
-                        basis(m, U, static_cast<double>(ba[CB][i]), cU, cA, A.inv_K, A.inv_tbar,
-                              phi);
-                        const double Y = D[i] * ik;
-#pragma unroll
-                        for (int q = 0; q < 5; ++q)
-                            if (q < m) b[q] += phi[q] * Y;
-                        if constexpr (KEEP) {
-                            hh[i] = h;
-                            xx[i] = phi[1];
-                            ww[i] = phi[3];
-                        }
-                    }
-                }
-            }
             if (ok) {
+                const double ik = idsc[k];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    // (converted here, not when the load lands: FP32 pairs held
+                    // as FP64 would take twice the registers)
+                    asm volatile("" : "+v"(cur[i].u), "+v"(cur[i].a));
+                    const double U = static_cast<double>(cur[i].u);
+                    const double x = (U - cU) * A.inv_K;
+                    const double w =
+                        m == 5 ? (static_cast<double>(cur[i].a) - cA) * A.inv_tbar : 0.0;
+                    // paths out of the money (or past P) add exact zeros
+                    const double Y = i < nlive && payoff(A.cp, A.K, U) > 0.0 ? D[i] * ik : 0.0;
+                    b[0] += Y;
+                    b[1] += x * Y;
+                    b[2] += (x * x) * Y;
+                    b[3] += w * Y;
+                    b[4] += (x * w) * Y;
+                }
                 // the inverse factor's loads fly during the exchange
                 double Lk[15];
 #pragma unroll
@@ -768,50 +746,29 @@ __global__ void __launch_bounds__(kClusterThreads,
                 skipped += 1.0;
                 have = false;
             }
-            // date k-2 into old, issued after the exchange, whose slot polls
-            // would otherwise wait for these loads (vector loads complete in
-            // order)
-            // (all Q loads issue without branches: a path past P reads the
-            // last path, whose value no decision or sum uses)
-            if (k - 2 >= k_lo) {
-                const R2<R>* __restrict__ Fn = F + static_cast<int64_t>(k - 2 - f0) * P;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const int64_t p = pbase + i * kClusterThreads;
-                    const R2<R> f = Fn[p < P ? p : P - 1];
-                    bu[OB][i] = f.u;
-                    ba[OB][i] = f.a;
-                }
-            }
             return true;
         };
 
-        using I0 = std::integral_constant<int, 0>;
-        using I1 = std::integral_constant<int, 1>;
-        using I2 = std::integral_constant<int, 2>;
         for (int k = k_top; k >= k_lo;) {
-            if (!step(k, I0{}, I2{})) return;
+            if (!step(k, fa, fb)) return;
             if (--k < k_lo) break;
-            if (!step(k, I1{}, I0{})) return;
-            if (--k < k_lo) break;
-            if (!step(k, I2{}, I1{})) return;
+            if (!step(k, fb, fa)) return;
             --k;
         }
         if (have) {  // exercise at date k_lo (1 in the last window): its buffer was cur last
-            switch ((k_top - k_lo) % 3) {
-            case 0: decide(k_lo, bu[0], ba[0]); break;
-            case 1: decide(k_lo, bu[1], ba[1]); break;
-            default: decide(k_lo, bu[2], ba[2]); break;
-            }
+            if ((k_top - k_lo) % 2 == 0)
+                decide(k_lo, fa);
+            else
+                decide(k_lo, fb);
         }
     }
 
     if (WIN && !A.win_last) {  // a window before the last: D waits in the workspace
-        double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase;
+        double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase + tid;
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             if (i < nlive) dstate[i * kClusterThreads] = D[i];
-        if (g == 0 && threadIdx.x == 0) {
+        if (g == 0 && tid == 0) {
             double* o = A.out + static_cast<int64_t>(s) * 4;
             o[2] = (A.win_first ? 0.0 : o[2]) + skipped;
         }
@@ -838,7 +795,7 @@ __global__ void __launch_bounds__(kClusterThreads,
     if (!cluster_exchange<1>(s2, 1, part + static_cast<int64_t>(n + 1) * row_len, G, g, par, C,
                              Ls))
         return;
-    if (g == 0 && threadIdx.x == 0) {
+    if (g == 0 && tid == 0) {
         double* o = A.out + static_cast<int64_t>(s) * 4;
         o[0] = mean;
         o[1] = sqrt(s2[0] / static_cast<double>(P - 1) / static_cast<double>(P));
@@ -877,25 +834,25 @@ hipError_t launch_sweep_r(int q, const LsmcArgs& a, int S, hipStream_t st)
     }
 }
 
-template <typename R, int Q, bool KEEP, bool WIN>
+template <typename R, int Q, bool WIN>
 hipError_t launch_cluster_t(const LsmcArgs& a, const ClusterArgs& c, int S_launch, size_t lds,
                             hipStream_t st)
 {
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, KEEP, WIN>),
+            reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, WIN>),
             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_sweep_cluster<R, Q, KEEP, WIN>), dim3(S_launch * c.G),
-                       dim3(kClusterThreads), lds, st, a, c);
+    hipLaunchKernelGGL((k_sweep_cluster<R, Q, WIN>), dim3(S_launch * c.G), dim3(kClusterThreads),
+                       lds, st, a, c);
     return hipGetLastError();
 }
 
-template <typename R, int Q, bool KEEP, bool WIN>
+template <typename R, int Q, bool WIN>
 int cluster_capacity_t(size_t lds)
 {
-    const void* f = reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, KEEP, WIN>);
+    const void* f = reinterpret_cast<const void*>(&k_sweep_cluster<R, Q, WIN>);
     if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(lds)) != hipSuccess)
         return 0;
@@ -909,6 +866,21 @@ int cluster_capacity_t(size_t lds)
     return per_cu * cus;
 }
 
+// Calls f with the paths-per-thread count q as a compile-time constant (the
+// counts cluster_q_supported admits).
+template <typename Ret, typename Fn>
+Ret with_q(int q, Ret bad, Fn&& f)
+{
+    switch (q) {
+#define HS_Q(Q) \
+    case Q: return f(std::integral_constant<int, Q>{});
+        HS_Q(1) HS_Q(2) HS_Q(3) HS_Q(4) HS_Q(5) HS_Q(6) HS_Q(7) HS_Q(8) HS_Q(10) HS_Q(12)
+        HS_Q(16)
+#undef HS_Q
+    default: return bad;
+    }
+}
+
 }  // namespace
 
 size_t cluster_lds_bytes(int n, int G)
@@ -918,44 +890,33 @@ size_t cluster_lds_bytes(int n, int G)
     return sizeof(double) * (2 * (kClusterThreads / 64) * kPartStride + 2 * kPartStride) + 16;
 }
 
-int cluster_capacity(int ft, int q, bool keep, bool win, size_t lds)
+int cluster_capacity(int ft, int q, bool win, size_t lds)
 {
-    if (keep && win) return 0;  // windows run the variant without kept basis values
+    if (!cluster_q_supported(q, ft)) return 0;
     return with_feat(ft, 0, [&](auto tag) -> int {
         using FT = std::remove_pointer_t<decltype(tag)>;
-        switch (q) {
-#define HS_CAP(Q)                                                                          \
-    case Q:                                                                                \
-        return keep  ? cluster_capacity_t<FT, Q, true, false>(lds)                         \
-               : win ? cluster_capacity_t<FT, Q, false, true>(lds)                         \
-                     : cluster_capacity_t<FT, Q, false, false>(lds);
-            HS_CAP(1) HS_CAP(2) HS_CAP(3) HS_CAP(4) HS_CAP(5) HS_CAP(6) HS_CAP(7) HS_CAP(8)
-#undef HS_CAP
-        default: return 0;
-        }
+        return with_q(q, 0, [&](auto qc) -> int {
+            constexpr int Q = decltype(qc)::value;
+            return win ? cluster_capacity_t<FT, Q, true>(lds) : cluster_capacity_t<FT, Q, false>(lds);
+        });
     });
 }
 
-hipError_t launch_sweep_cluster(int ft, int q, bool keep, const LsmcArgs& a,
-                                const ClusterArgs& c, int S_launch, hipStream_t st)
+hipError_t launch_sweep_cluster(int ft, int q, const LsmcArgs& a, const ClusterArgs& c,
+                                int S_launch, hipStream_t st)
 {
     const size_t lds = cluster_lds_bytes(a.n, c.G);
     const bool win = a.k_lo != 1 || a.k_hi != a.n || !a.win_first || !a.win_last;
-    if (win && (keep || !a.american || !a.cf || a.k_lo < 1 || a.k_hi > a.n || a.f_date0 > a.k_lo))
+    if (win && (!a.american || !a.cf || a.k_lo < 1 || a.k_hi > a.n || a.f_date0 > a.k_lo))
         return hipErrorInvalidValue;
+    if (!cluster_q_supported(q, ft)) return hipErrorInvalidValue;
     return with_feat(ft, hipErrorInvalidValue, [&](auto tag) -> hipError_t {
         using FT = std::remove_pointer_t<decltype(tag)>;
-        switch (q) {
-#define HS_LAUNCH(Q)                                                                    \
-    case Q:                                                                             \
-        return keep  ? launch_cluster_t<FT, Q, true, false>(a, c, S_launch, lds, st)    \
-               : win ? launch_cluster_t<FT, Q, false, true>(a, c, S_launch, lds, st)    \
-                     : launch_cluster_t<FT, Q, false, false>(a, c, S_launch, lds, st);
-            HS_LAUNCH(1) HS_LAUNCH(2) HS_LAUNCH(3) HS_LAUNCH(4) HS_LAUNCH(5) HS_LAUNCH(6)
-            HS_LAUNCH(7) HS_LAUNCH(8)
-#undef HS_LAUNCH
-        default: return hipErrorInvalidValue;
-        }
+        return with_q(q, hipErrorInvalidValue, [&](auto qc) -> hipError_t {
+            constexpr int Q = decltype(qc)::value;
+            return win ? launch_cluster_t<FT, Q, true>(a, c, S_launch, lds, st)
+                       : launch_cluster_t<FT, Q, false>(a, c, S_launch, lds, st);
+        });
     });
 }
 

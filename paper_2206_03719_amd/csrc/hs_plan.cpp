@@ -385,20 +385,18 @@ Shape shape_of(const Request& q)
                                                           : kFeatF32;
     // cluster sweep shape from the request alone (never from device load, nor
     // from the workspace): spread the Greek set's scenarios over the compute
-    // units, from one path per thread up to 8
+    // units, from one path per thread up to the most that two workgroups per
+    // CU hold (a set larger than the device runs in several launches, each a
+    // chain of exchanges: more paths per thread, fewer launches)
     const int64_t P = q.P;
     const int64_t T = kClusterThreads;
     const int64_t S = num_scenarios(q.N, q.bumps.mask);
-    int64_t gmin = (P + 8 * T - 1) / (8 * T);
-    // more workgroups than one per CU: throughput-bound, two workgroups per CU,
-    // which bounds the paths per thread
-    if (S * gmin > kPlanComputeUnits) {
-        const int64_t qs = cluster_qmax_shared(q.opts.precision == HS_FP32_PATHS);
-        gmin = (P + qs * T - 1) / (qs * T);
-    }
+    const int64_t qmax = cluster_qmax(sh.feat);
+    int64_t gmin = (P + qmax * T - 1) / (qmax * T);
     const int64_t gone = (P + T - 1) / T;
     int64_t G = std::max(gmin, std::min(std::max<int64_t>(1, kPlanComputeUnits / std::max<int64_t>(S, 1)), gone));
-    const int cq = static_cast<int>((P + G * T - 1) / (G * T));
+    int cq = static_cast<int>((P + G * T - 1) / (G * T));
+    while (!cluster_q_supported(cq, sh.feat)) ++cq;  // 9 -> 10, 13 -> 16, ...
     G = (P + cq * T - 1) / (cq * T);
     sh.cluster_q = cq;
     sh.cluster_g = static_cast<int>(G);
