@@ -665,6 +665,12 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
     double beta[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     bool have = false;  // beta of the later date k+1 is valid
     double skipped = 0.0;
+    // payoff h = max(sg U - sg K, 0) as one FMA (sg = -1 put, +1 call: the
+    // same rounding as K - U or U - K); basis x = U/K - cU/K and w = A/tbar -
+    // cA/tbar as one FMA each (w = 0 for the quadratic basis)
+    const double sg = A.cp == 0 ? -1.0 : 1.0;
+    const double sK = sg * A.K;
+    const double iw = m == 5 ? A.inv_tbar : 0.0;
     if (A.american) {
         R2<R> fa[Q], fb[Q];
         if (k_top >= k_lo) load(k_top, fa);
@@ -672,7 +678,7 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
         double r_ok = k_top >= k_lo ? recs[k_top - 1].ok : 0.0;
         double r_cU = k_top >= k_lo ? recs[k_top - 1].cU : 0.0;
         double r_cA = k_top >= k_lo ? recs[k_top - 1].cA : 0.0;
-        double bcU = 0.0, bcA = 0.0;  // regression-set means of date k+1
+        double bcU = 0.0, bcA = 0.0;  // regression-set means of date k+1, as cU/K, cA/tbar
 
         // the exercise decision at date kd with that date's regression (beta,
         // bcU, bcA) and features.  The basis values are recomputed from the
@@ -685,11 +691,12 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
             for (int i = 0; i < Q; ++i) {
                 asm volatile("" : "+v"(f[i].u), "+v"(f[i].a));
                 const double U = static_cast<double>(f[i].u);
-                const double h = payoff(A.cp, A.K, U);
-                const double x = (U - bcU) * A.inv_K;
-                const double w = m == 5 ? (static_cast<double>(f[i].a) - bcA) * A.inv_tbar : 0.0;
-                const double cont = beta[0] + beta[1] * x + beta[2] * (x * x) + beta[3] * w +
-                                    beta[4] * (x * w);
+                const double h = fmax(fma(U, sg, -sK), 0.0);
+                const double x = fma(U, A.inv_K, -bcU);
+                const double w = fma(static_cast<double>(f[i].a), iw, -bcA);
+                // beta_0 + beta_1 x + beta_2 x^2 + beta_3 w + beta_4 x w
+                const double cont =
+                    fma(x, fma(beta[4], w, fma(beta[2], x, beta[1])), fma(beta[3], w, beta[0]));
                 const bool ex = i < nlive && h > 0.0 && h > cont;
                 D[i] = ex ? h * d1 : D[i];
                 if (tau && ex) tau[i * kClusterThreads] = kd;
@@ -699,7 +706,7 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
         // one date k (cur: date k, old: date k + 1); false if a wait timed out
         auto step = [&](int k, R2<R>(&cur)[Q], R2<R>(&old)[Q]) -> bool {
             const bool ok = r_ok != 0.0;
-            const double cU = r_cU, cA = r_cA;
+            const double cU = r_cU * A.inv_K, cA = r_cA * iw;
             if (k > k_lo) {
                 r_ok = recs[k - 2].ok;
                 r_cU = recs[k - 2].cU;
@@ -709,26 +716,27 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
             // loads into its buffer, then this date's right-hand side with the
             // updated cash flows
             if (have) decide(k + 1, old);
-            if (k - 1 >= k_lo) load(k - 1, old);
+            // unconditional (the last date reloads itself, unused): a load
+            // under a branch would leave the compiler unsure how many loads
+            // are in flight, and it would wait for all of them before the
+            // right-hand side
+            load(max(k - 1, k_lo), old);
             double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             if (ok) {
                 const double ik = idsc[k];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    // (converted here, not when the load lands: FP32 pairs held
-                    // as FP64 would take twice the registers)
-                    asm volatile("" : "+v"(cur[i].u), "+v"(cur[i].a));
                     const double U = static_cast<double>(cur[i].u);
-                    const double x = (U - cU) * A.inv_K;
-                    const double w =
-                        m == 5 ? (static_cast<double>(cur[i].a) - cA) * A.inv_tbar : 0.0;
+                    const double x = fma(U, A.inv_K, -cU);
+                    const double w = fma(static_cast<double>(cur[i].a), iw, -cA);
                     // paths out of the money (or past P) add exact zeros
-                    const double Y = i < nlive && payoff(A.cp, A.K, U) > 0.0 ? D[i] * ik : 0.0;
+                    const double Y = i < nlive && fma(U, sg, -sK) > 0.0 ? D[i] * ik : 0.0;
+                    const double xY = x * Y;
                     b[0] += Y;
-                    b[1] += x * Y;
-                    b[2] += (x * x) * Y;
-                    b[3] += w * Y;
-                    b[4] += (x * w) * Y;
+                    b[1] += xY;
+                    b[2] = fma(x, xY, b[2]);
+                    b[3] = fma(w, Y, b[3]);
+                    b[4] = fma(w, xY, b[4]);
                 }
                 // the inverse factor's loads fly during the exchange
                 double Lk[15];
