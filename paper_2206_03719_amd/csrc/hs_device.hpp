@@ -157,6 +157,18 @@ __device__ __forceinline__ R pick(const R (&arr)[NM], int i)
     return pick_from<1>(arr, i, arr[0]);
 }
 
+// Relaxed workgroup-scope atomic LDS accesses (plain ds_write / ds_read).
+template <typename T>
+__device__ __forceinline__ void lds_put(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ T lds_get(T* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // ---------------------------------------------------------------------------
 // Andersen's quadratic-exponential step of one asset from (X, v) (constants
 // c: QeP) with the asset's correlated spot normal zs = (L eps)_i and its own

@@ -78,9 +78,11 @@ int paths_nmax_bucket(int N)
 
 size_t paths_lds_bytes(bool fp32, int scheme, int nmax)
 {
-    // two parities of eps, eta, Z^S (FP64 under QE), exp(X) and max(v, 0)
+    // two parities of eps and eta, one of Z^S (FP64 under QE), exp(X) and
+    // max(v, 0), and three prefix tables of nmax + 1 entries
     const size_t r = fp32 ? 4u : 8u, z = scheme == HS_SCHEME_QE ? 8u : r;
-    return 2u * static_cast<size_t>(nmax) * kLanes * (3u * z + 2u * r);
+    const size_t slab = static_cast<size_t>(nmax) * kLanes;
+    return slab * (5u * z + 2u * r) + 3u * static_cast<size_t>(nmax + 1) * kLanes * r;
 }
 
 hipError_t launch_paths(bool fp32, int nmax, int scheme, int ft, const PathArgs& a, int nchunks,

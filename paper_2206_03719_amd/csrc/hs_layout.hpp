@@ -24,7 +24,7 @@ constexpr int paths_tmax_for(bool fp32, bool qe, int nmax)
 {
     return !fp32 ? (nmax > 8 ? nmax : 8)
            : qe  ? (nmax > 16 ? nmax : 16)
-                 : (nmax <= 8 ? 32 : nmax <= 12 ? 24 : 20);
+                 : (nmax <= 8 ? 24 : nmax <= 12 ? 20 : nmax);
 }
 
 // Most waves per block of the Greek-set path kernel for a variant.  FP64 at
@@ -38,6 +38,7 @@ constexpr int paths_max_waves(bool fp32, int nmax)
 {
     return (!fp32 && nmax == 16) ? 4 : kMaxWaves;
 }
+
 
 // Storage type of the path features (U, A) in the workspace.
 enum FeatType { kFeatF32 = 0, kFeatF64 = 1, kFeatF16 = 2, kFeatBF16 = 3 };

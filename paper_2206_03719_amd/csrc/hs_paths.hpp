@@ -21,11 +21,14 @@ namespace {
 //
 // Block = W waves x 64 lanes; lane l of every wave follows path
 // 64 * blockIdx.x + l.  blockIdx.y selects a "block group": W groups (one per
-// wave) of tasks.  LDS holds, double-buffered by step parity, the step's
-// normals (eps, eta), the base scenario's correlated normals Z^S, exp(X) and
-// max(v, 0), each [asset][lane]; under QE the normals eps, eta, Z^S and the
-// variance state are FP64 (ZT, VT) in both path precisions, so the variance
-// path is the FP64 one.
+// wave) of tasks.  LDS holds, each [asset][lane]: the step's normals (eps,
+// eta), double-buffered by step parity (a fast wave draws step k + 1 while a
+// slow one still reads step k's eta); the base scenario's correlated normals
+// Z^S, exp(X) and max(v, 0), and the prefix tables of the base features
+// (single buffers: a step's writes come after its first barrier, which every
+// wave reaches only once it has finished the previous step).  Under QE the
+// normals eps, eta, Z^S and the variance state are FP64 (ZT, VT) in both
+// path precisions, so the variance path is the FP64 one.
 template <typename R, int NMAX, int TMAX, int SCHEME, typename FT, bool CK>
 __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX))
     k_paths(const PathArgs A)
@@ -33,10 +36,19 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
     using VT = std::conditional_t<SCHEME == HS_SCHEME_QE, double, R>;
     using ZT = VT;  // the spot normals eps and Z^S = L eps
     extern __shared__ unsigned char hs_smem[];
-    constexpr int SLAB = NMAX * kLanes;  // one [asset][lane] array
-    // per parity: eps, eta, Z^S, exp(X), max(v, 0)
-    constexpr size_t SZ = SLAB * sizeof(ZT), SR = SLAB * sizeof(R);
-    constexpr size_t PAR = 3 * SZ + 2 * SR;
+    constexpr int SLAB = NMAX * kLanes;          // one [asset][lane] array
+    constexpr int XSLAB = (NMAX + 1) * kLanes;   // one prefix table
+    constexpr size_t SZ = SLAB * sizeof(ZT), SR = SLAB * sizeof(R), SX = XSLAB * sizeof(R);
+    constexpr size_t PAR = 2 * SZ;               // eps and eta of one parity
+    ZT* const s_zs = reinterpret_cast<ZT*>(hs_smem + 2 * PAR);
+    R* const s_e = reinterpret_cast<R*>(hs_smem + 2 * PAR + SZ);
+    R* const s_vp = reinterpret_cast<R*>(hs_smem + 2 * PAR + SZ + SR);
+    // prefix tables of the base scenario, entry j of [0, N]: the largest
+    // price and the sum of max(v, 0) over assets < j (pmx, psx), the largest
+    // price over assets >= j (smx; 0 at j = N)
+    R* const s_pmx = reinterpret_cast<R*>(hs_smem + 2 * PAR + SZ + 2 * SR);
+    R* const s_psx = reinterpret_cast<R*>(hs_smem + 2 * PAR + SZ + 2 * SR + SX);
+    R* const s_smx = reinterpret_cast<R*>(hs_smem + 2 * PAR + SZ + 2 * SR + 2 * SX);
 
     const int lane = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -118,9 +130,6 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
         unsigned char* const pb = hs_smem + (k & 1) * PAR;
         ZT* const s_eps = reinterpret_cast<ZT*>(pb);
         VT* const s_eta = reinterpret_cast<VT*>(pb + SZ);
-        ZT* const s_zs = reinterpret_cast<ZT*>(pb + 2 * SZ);
-        R* const s_e = reinterpret_cast<R*>(pb + 3 * SZ);
-        R* const s_vp = reinterpret_cast<R*>(pb + 3 * SZ + SR);
 
         // 1) Philox blocks j = w, w + W, ...: pair 2j <- (w0, w1), 2j+1 <- (w2, w3)
         for (int j = w; j < nblk; j += W) {
@@ -169,54 +178,61 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
                               : (A.store_all || k == A.n - 1);
         const int64_t off =
             (A.store_all ? static_cast<int64_t>(CK ? k - A.k_feat0 : k) * P : 0) + p;
+        // the base scenario's prices Sb and prefix tables, streamed into LDS:
+        // every wave writes the same tables (identical values from identical
+        // inputs) and then reads entries back -- relaxed atomic accesses, so
+        // the overlapping writes are no data race, and a wave's own write
+        // precedes its reads
         ZT eps[NMAX];
-        R E[NMAX], Sb[NMAX], vpb[NMAX], pm[NMAX], sm[NMAX], ps[NMAX];
+        R Sb[NMAX];
+        R bsum = R(0), run = R(0);
+        lds_put(s_pmx + lane, R(0));
+        lds_put(s_psx + lane, R(0));
 #pragma unroll
         for (int a = 0; a < NMAX; ++a) {
             if (a < N) {
                 eps[a] = s_eps[a * kLanes + lane];
-                E[a] = s_e[a * kLanes + lane];
-                Sb[a] = bp->a[a].S0 * E[a];
-                vpb[a] = s_vp[a * kLanes + lane];
+                Sb[a] = bp->a[a].S0 * s_e[a * kLanes + lane];
+                run = a == 0 ? Sb[0] : (Sb[a] > run ? Sb[a] : run);
+                bsum = bsum + s_vp[a * kLanes + lane];
+                lds_put(s_pmx + (a + 1) * kLanes + lane, run);
+                lds_put(s_psx + (a + 1) * kLanes + lane, bsum);
             } else {
                 eps[a] = ZT(0);
-                E[a] = R(0);
                 Sb[a] = R(0);
-                vpb[a] = R(0);
             }
         }
-        // prefix max / prefix sum / suffix max of the base scenario (entries
-        // past N are 0, and every S > 0, so the padding never wins a max)
-        R bsum = R(0);
-        pm[0] = Sb[0];
+        // suffix maxima (every S > 0; 0 past the last asset)
+        R suf = R(0);
+        lds_put(s_smx + N * kLanes + lane, R(0));
 #pragma unroll
-        for (int a = 1; a < NMAX; ++a) pm[a] = Sb[a] > pm[a - 1] ? Sb[a] : pm[a - 1];
-#pragma unroll
-        for (int a = 0; a < NMAX; ++a) {
-            if (a < N) bsum = bsum + vpb[a];
-            ps[a] = bsum;
+        for (int a = NMAX - 1; a >= 0; --a) {
+            if (a < N) {
+                suf = Sb[a] > suf ? Sb[a] : suf;
+                lds_put(s_smx + a * kLanes + lane, suf);
+            }
         }
-        sm[NMAX - 1] = Sb[NMAX - 1];
-#pragma unroll
-        for (int a = NMAX - 2; a >= 0; --a) sm[a] = Sb[a] > sm[a + 1] ? Sb[a] : sm[a + 1];
         const R bA = bsum * invN;
 
         if (store && live) {
             if (g_base >= 0) {
                 R2<FT> f;
-                f.u = static_cast<FT>(sm[0]);
+                f.u = static_cast<FT>(suf);
                 f.a = static_cast<FT>(bA);
                 feat[g_base * A.plane + off] = f;
             }
             if (g_up0 >= 0) {
+                // a spot bump rescales one asset of the base path; the other
+                // assets' largest price comes from the prefix tables
 #pragma unroll
                 for (int a = 0; a < NMAX; ++a) {
                     if (a < N) {
-                        const R lo = a > 0 ? pm[a > 0 ? a - 1 : 0] : R(0);
-                        const R hi = a + 1 < NMAX ? sm[a + 1 < NMAX ? a + 1 : a] : R(0);
+                        const R lo = lds_get(s_pmx + a * kLanes + lane);
+                        const R hi = lds_get(s_smx + (a + 1) * kLanes + lane);
                         const R ex = lo > hi ? lo : hi;
-                        const R su = bp->S0_up[a] * E[a];
-                        const R sd = bp->S0_dn[a] * E[a];
+                        const R E = s_e[a * kLanes + lane];
+                        const R su = bp->S0_up[a] * E;
+                        const R sd = bp->S0_dn[a] * E;
                         R2<FT> f;
                         f.a = static_cast<FT>(bA);
                         f.u = static_cast<FT>(su > ex ? su : ex);
@@ -228,25 +244,29 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
             }
         }
 
-        // 4) this wave's tasks (assets of bumped scenarios that leave the base path)
+        // 4) this wave's tasks (assets of bumped scenarios that leave the base
+        //    path); a scenario's own assets [lo, hi) are consecutive tasks,
+        //    joined to the base's assets outside them through the prefix tables
         R runM = R(0), runS = R(0);
 #pragma unroll
         for (int t = 0; t < TMAX; ++t) {
             if (t < ntask) {
                 const cptr<TaskP<R>> T = tk + t;
                 const int a = T->asset;
-                ZT z;
-                if (T->own_row) {
-                    cptr<ZT> tL;
-                    if constexpr (std::is_same_v<ZT, R>)
-                        tL = T->L;
-                    else
-                        tL = T->L64;
-                    z = ZT(0);
+                ZT z = ZT(0);
+                if constexpr (SCHEME == HS_SCHEME_QE) {
+                    if (T->own_row) {
 #pragma unroll
-                    for (int b = 0; b < NMAX; ++b) z += tL[b] * eps[b];
+                        for (int b = 0; b < NMAX; ++b) z += T->L64[b] * eps[b];
+                    } else {
+                        z = s_zs[a * kLanes + lane];
+                    }
                 } else {
-                    z = s_zs[a * kLanes + lane];
+                    // the scenario's Cholesky row (the base row where the bump
+                    // leaves it): the same FMA chain as the base step's, so
+                    // equal rows give equal Z^S
+#pragma unroll
+                    for (int b = 0; b < NMAX; ++b) z += T->L[b] * eps[b];
                 }
                 if constexpr (SCHEME == HS_SCHEME_QE) {
                     qe_step(&T->qe, z, s_eta[a * kLanes + lane], tX[t], tV[t]);
@@ -259,18 +279,20 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
                 }
                 const R S = T->S0 * exp_r(tX[t]);
                 const R vpt = static_cast<R>(tV[t] > VT(0) ? tV[t] : VT(0));
-                if (T->first) {
-                    runM = T->lo > 0 ? pick(pm, T->lo - 1) : R(0);
-                    runS = T->lo > 0 ? pick(ps, T->lo - 1) : R(0);
-                }
+                const int lo = T->lo;
+                const R m0 = lds_get(s_pmx + lo * kLanes + lane);
+                const R s0 = lds_get(s_psx + lo * kLanes + lane);
+                const bool first = T->first != 0;
+                runM = first ? m0 : runM;
+                runS = first ? s0 : runS;
                 runM = S > runM ? S : runM;
                 runS = runS + vpt;
                 if (T->last) {
-                    if (T->hi < N) {
-                        const R tail = pick(sm, T->hi);
-                        runM = tail > runM ? tail : runM;
-                        runS = runS + (bsum - pick(ps, T->hi - 1));
-                    }
+                    const int hi = T->hi;
+                    const R tail = lds_get(s_smx + hi * kLanes + lane);
+                    runM = tail > runM ? tail : runM;
+                    runS = runS + (lds_get(s_psx + N * kLanes + lane) -
+                                   lds_get(s_psx + hi * kLanes + lane));
                     if (store && live) {
                         R2<FT> f;
                         f.u = static_cast<FT>(runM);

@@ -172,7 +172,10 @@ def test_cancel_and_errors():
     _wait(srv, [t1])
     with pytest.raises(hs.HSError):
         srv.poll(t1)  # retired
-    big = W.best_of_call(n_assets=20, n_paths=400000, n_steps=504)
+    # a request whose minimum workspace (about 10 GiB) exceeds the 4 GiB pool
+    big = W.best_of_call(n_assets=20, n_paths=1000000, n_steps=504)
+    assert hs.workspace_bytes(big["model"], big["option"], 1000000, 504, big["bumps"],
+                              minimum=True) > (4 << 30)
     with pytest.raises(hs.HSError) as e:
         srv.submit(big)
     assert e.value.status == hs.ENOMEM
