@@ -384,7 +384,7 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         pa.groups = reinterpret_cast<const GroupP*>(ws + pp.lay.groups);
         pa.feat = ws + pp.lay.feat;
         pa.P = q.P;
-        pa.plane = (sh.american ? static_cast<int64_t>(q.n) : 1) * q.P;
+        pa.plane = pp.plane;
         pa.n = q.n;
         pa.N = q.N;
         pa.W = pp.W;
@@ -395,7 +395,6 @@ hs_status run_greek_set(const Request& q, void* d_ws, size_t ws_bytes, hipStream
         pa.k_end = q.n;
         pa.k_feat0 = 0;
         L.window = sh.american ? pass.window : 0;
-        if (L.window > 0) pa.plane = static_cast<int64_t>(L.window) * q.P;
         pa.ck_every = L.window;
         pa.ck_store = 0;
         pa.ck_slots = q.N + pp.ntasks;

@@ -79,11 +79,21 @@ struct BaseP {
 // from the base one (v0, T, r or correlation bumps).  Tasks of a scenario
 // are contiguous, in asset order, and cover the scenario's own asset range
 // [lo, hi); assets outside it are the base scenario's, bit for bit.
+//
+// The fields of the Euler step come first and in one block, so that the
+// kernel reads them with a few wide scalar loads: offsets of the asset's,
+// lo's and hi's [asset][lane] rows (x kLanes), the flags first | last << 1,
+// the scenario's feature-plane offset, the step constants and the Cholesky
+// row.
 template <typename R>
 struct TaskP {
+    int32_t a_el, lo_el, hi_el, flags;
+    int64_t fo;       // scen * plane
+    R S0, rho, rhobar, dt, r, kappa, theta, xi;
+    R L[kMaxAssets];  // the scenario's Cholesky row of `asset` (the base row
+                      // where the bump leaves it)
     int32_t asset, own_row, first, last, scen, lo, hi, pad;
-    R S0, v0, kappa, theta, xi, rho, rhobar, r, dt, pad1;
-    R L[kMaxAssets];  // the scenario's Cholesky row of `asset` (own_row == 1)
+    R v0, pad1;
     double L64[kMaxAssets];  // the same in FP64 (QE)
     QeP<R> qe;
 };

@@ -252,26 +252,25 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
         for (int t = 0; t < TMAX; ++t) {
             if (t < ntask) {
                 const cptr<TaskP<R>> T = tk + t;
-                const int a = T->asset;
+                // the Euler step's constants lead the record: a few wide
+                // scalar loads
+                const int a_el = T->a_el, lo_el = T->lo_el, hi_el = T->hi_el, flags = T->flags;
                 ZT z = ZT(0);
                 if constexpr (SCHEME == HS_SCHEME_QE) {
                     if (T->own_row) {
 #pragma unroll
                         for (int b = 0; b < NMAX; ++b) z += T->L64[b] * eps[b];
                     } else {
-                        z = s_zs[a * kLanes + lane];
+                        z = s_zs[a_el + lane];
                     }
+                    qe_step(&T->qe, z, s_eta[a_el + lane], tX[t], tV[t]);
                 } else {
                     // the scenario's Cholesky row (the base row where the bump
                     // leaves it): the same FMA chain as the base step's, so
                     // equal rows give equal Z^S
 #pragma unroll
                     for (int b = 0; b < NMAX; ++b) z += T->L[b] * eps[b];
-                }
-                if constexpr (SCHEME == HS_SCHEME_QE) {
-                    qe_step(&T->qe, z, s_eta[a * kLanes + lane], tX[t], tV[t]);
-                } else {
-                    const R zv = T->rho * z + T->rhobar * s_eta[a * kLanes + lane];
+                    const R zv = T->rho * z + T->rhobar * s_eta[a_el + lane];
                     const R vp = tV[t] > R(0) ? tV[t] : R(0);
                     const R sq = sqrt_r(vp * T->dt);
                     tX[t] = tX[t] + (T->r - half * vp) * T->dt + sq * z;
@@ -279,25 +278,23 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
                 }
                 const R S = T->S0 * exp_r(tX[t]);
                 const R vpt = static_cast<R>(tV[t] > VT(0) ? tV[t] : VT(0));
-                const int lo = T->lo;
-                const R m0 = lds_get(s_pmx + lo * kLanes + lane);
-                const R s0 = lds_get(s_psx + lo * kLanes + lane);
-                const bool first = T->first != 0;
+                const R m0 = lds_get(s_pmx + lo_el + lane);
+                const R s0 = lds_get(s_psx + lo_el + lane);
+                const R tail = lds_get(s_smx + hi_el + lane);
+                const R ptail = lds_get(s_psx + N * kLanes + lane) - lds_get(s_psx + hi_el + lane);
+                const bool first = (flags & 1) != 0;
                 runM = first ? m0 : runM;
                 runS = first ? s0 : runS;
                 runM = S > runM ? S : runM;
                 runS = runS + vpt;
-                if (T->last) {
-                    const int hi = T->hi;
-                    const R tail = lds_get(s_smx + hi * kLanes + lane);
+                if (flags & 2) {
                     runM = tail > runM ? tail : runM;
-                    runS = runS + (lds_get(s_psx + N * kLanes + lane) -
-                                   lds_get(s_psx + hi * kLanes + lane));
+                    runS = runS + ptail;
                     if (store && live) {
                         R2<FT> f;
                         f.u = static_cast<FT>(runM);
                         f.a = static_cast<FT>(runS * invN);
-                        feat[T->scen * A.plane + off] = f;
+                        feat[T->fo + off] = f;
                     }
                 }
             }

@@ -601,6 +601,11 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
                     t.L[c] = static_cast<R>(s.L[a * N + c]);
                     t.L64[c] = s.L[a * N + c];
                 }
+                t.a_el = a * kLanes;
+                t.lo_el = s.lo * kLanes;
+                t.hi_el = s.hi * kLanes;
+                t.flags = (t.first ? 1 : 0) | (t.last ? 2 : 0);
+                t.fo = static_cast<int64_t>(t.scen) * pp.plane;
                 tasks.push_back(t);
             }
         }
@@ -670,6 +675,8 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
     W = std::min(W, paths_max_waves(sh.fp32, sh.nmax));
     pp.W = W;
     pp.nbg = static_cast<int>((gs.size() + W - 1) / W);
+    // dates stored per scenario: all (American), a window of them, or the last
+    pp.plane = (sh.american ? static_cast<int64_t>(pass.window > 0 ? pass.window : q.n) : 1) * q.P;
     if (sh.fp32)
         fill_tables<float>(q, sh, sc, pass, gs, pp);
     else

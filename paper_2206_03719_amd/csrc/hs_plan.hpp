@@ -98,6 +98,7 @@ struct PassPlan {
     std::vector<GroupP> groups;         // [nbg * W]
     std::vector<double> disc;           // [scen][n+1] exp(-r j dt), then [scen][n+1] exp(+r j dt)
     int W = 1, nbg = 1, nchunks = 1, ntasks = 0;
+    int64_t plane = 0;  // feature elements per scenario plane (dates stored x P)
     Layout lay;
 };
 
