@@ -122,10 +122,17 @@ __device__ __forceinline__ cptr<T> as_const(const void* p)
 // lane offset, so callers put the whole offset there and pass soff = 0), and
 // a ragged last chunk of paths needs no clamped addresses.  Descriptor word
 // 3, 0x00020000, is the raw (unformatted) buffer of the GFX9 family's
-// resource layout.
+// resource layout.  p and bytes must be wave-uniform: they are read from the
+// first active lane, so the descriptor lives in scalar registers (a
+// descriptor the compiler takes for divergent costs a loop per load).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_over(const void* p, uint32_t bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes),
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(a >> 32));
+    void* const q = reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, 0,
+                                             static_cast<int>(__builtin_amdgcn_readfirstlane(bytes)),
                                              0x00020000);
 }
 template <typename T>

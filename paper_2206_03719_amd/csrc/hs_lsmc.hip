@@ -687,6 +687,11 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
         // does not keep those (4 more registers per path) across the exchange.
         auto decide = [&](int kd, R2<R>(&f)[Q]) {
             const double d1 = dsc[kd];
+            // the live-path count, opaque to the compiler here: it compares
+            // i < nl where the decision needs it instead of keeping Q masks
+            // (2 Q scalar registers) alive across the whole loop
+            int nl = nlive;
+            asm volatile("" : "+v"(nl));
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 asm volatile("" : "+v"(f[i].u), "+v"(f[i].a));
@@ -697,7 +702,7 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
                 // beta_0 + beta_1 x + beta_2 x^2 + beta_3 w + beta_4 x w
                 const double cont =
                     fma(x, fma(beta[4], w, fma(beta[2], x, beta[1])), fma(beta[3], w, beta[0]));
-                const bool ex = i < nlive && h > 0.0 && h > cont;
+                const bool ex = i < nl && h > 0.0 && h > cont;
                 D[i] = ex ? h * d1 : D[i];
                 if (tau && ex) tau[i * kClusterThreads] = kd;
             }
@@ -729,8 +734,9 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
                     const double U = static_cast<double>(cur[i].u);
                     const double x = fma(U, A.inv_K, -cU);
                     const double w = fma(static_cast<double>(cur[i].a), iw, -cA);
-                    // paths out of the money (or past P) add exact zeros
-                    const double Y = i < nlive && fma(U, sg, -sK) > 0.0 ? D[i] * ik : 0.0;
+                    // paths out of the money add exact zeros, and so do paths
+                    // past P (their D stays 0: decide never exercises them)
+                    const double Y = fma(U, sg, -sK) > 0.0 ? D[i] * ik : 0.0;
                     const double xY = x * Y;
                     b[0] += Y;
                     b[1] += xY;
