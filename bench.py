@@ -507,6 +507,8 @@ def _saturated(hs, srv, n_req):
                 p = srv.poll(t)
                 if p is not None:
                     done[t] = p
+                    if len(done) % 100 == 0:
+                        log("saturated: %d of %d requests done" % (len(done), len(tickets)))
         time.sleep(0.001)
     t_sat = time.perf_counter() - t0
     steps = sum(hs.num_scenarios(len(r["model"]["S0"]), 31) * r["n_paths"] * r["n_steps"]
@@ -532,6 +534,9 @@ def _poisson_run(hs, srv, n_req, rate, seed):
             if p is not None:
                 lat.append(p[1])
                 del pending[t]
+                if len(lat) % 100 == 0:
+                    log("poisson stream at %.2f requests/s: %d of %d done"
+                        % (rate, len(lat), len(stream)))
         time.sleep(0.0005)
     t_run = time.perf_counter() - t0
     steps = sum(hs.num_scenarios(len(r["model"]["S0"]), 31) * r["n_paths"] * r["n_steps"]
