@@ -511,7 +511,12 @@ __device__ __forceinline__ bool cluster_exchange(double (&b)[K], int m, double* 
                                                  int par, const ClusterArgs& C, const ClusterLds& L)
 {
     constexpr int NW = kClusterThreads / 64;
-    const int lane = threadIdx.x & 63;
+    // lane and m made opaque here, so that the compiler recomputes the
+    // conditions on them at each exchange instead of keeping their masks in
+    // scalar registers across the whole date loop
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    asm volatile("" : "+s"(m));
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
     for (int q = 0; q < K; ++q) b[q] = wave_sum_lane63(b[q]);
@@ -726,7 +731,8 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
             // are in flight, and it would wait for all of them before the
             // right-hand side
             load(max(k - 1, k_lo), old);
-            double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            // -0.0 + y == y for every y, so the first path's terms need no add
+            double b[5] = {-0.0, -0.0, -0.0, -0.0, -0.0};
             if (ok) {
                 const double ik = idsc[k];
 #pragma unroll
