@@ -87,22 +87,24 @@ def path_kernel_slots(N, P, n, mask):
     full-truncation Euler step with its correlation row costs 25 + (N+1)/2
     slots (two sqrt and one exp at quarter rate, ~13 other operations) and is
     paid for every element whose path differs from the base path: the base's
-    N assets, plus the assets at and after the bumped one for the v0 and
-    correlation scenarios and all N for the maturity and rate scenarios.
-    Spot scenarios rescale one asset of the base path: 4 slots each."""
+    N assets, plus the bumped asset for the v0 scenarios, the assets at and
+    after the later asset of the pair for the correlation scenarios and all N
+    for the maturity scenario.  Spot scenarios rescale one asset of the base
+    path, and the rate scenario all of them by one factor e^{(r' - r) t} (the
+    rate enters the log price only through its drift): 4 slots each."""
     own = N  # base
-    spot = 0
+    scaled = 0
     if mask & 1:
-        spot = 2 * N
+        scaled += 2 * N
     if mask & 2:
         own += N              # each v0 bump changes only its own asset
     if mask & 4:
         own += N              # maturity: a new time step for every asset
     if mask & 8:
-        own += N              # rate: new drift for every asset
+        scaled += 1           # rate: the base path's U times e^{(r' - r) t}
     if mask & 16:
         own += sum(N - j for j in range(1, N) for _ in range(j))  # rows j.. of L
-    per_path_step = 70 * N + (25 + (N + 1) / 2) * own + 4 * spot
+    per_path_step = 70 * N + (25 + (N + 1) / 2) * own + 4 * scaled
     return per_path_step * P * n
 
 

@@ -638,15 +638,16 @@ hs_status hs_autotune(const hs_model* model, const double* corr, const hs_option
     q.opts.waves_per_block = 0;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     // target waves (the default first) x the most waves per block (1: as
-    // few as the base assets allow); measured on the 5- and 10-asset sets,
-    // the best shape ranges from 8 waves per block at 25k paths to 3 at
-    // 200k paths with 10 assets
+    // few as the base assets allow)
     const int waves[] = {default_target_waves(), 1024, 8192};
-    static const int wmaxes[] = {1, 2, 3, 4, 6, 8};
+    static const int wmaxes[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    const Shape tsh = shape_of(q);
+    const int vmax = paths_max_waves(tsh.fp32, q.opts.scheme == HS_SCHEME_QE, tsh.nmax);
     Tune best{};
     double best_t = 1e300;
     for (int tw : waves)
         for (int wm : wmaxes) {
+            if (wm > vmax) continue;  // the planner caps it at the variant's most
             const Tune t{tw, wm};
             RunResult res;
             rc = run_greek_set(q, d_workspace, workspace_bytes, st, res, &t);  // warm-up

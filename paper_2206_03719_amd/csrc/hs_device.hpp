@@ -88,6 +88,9 @@ __device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, double& e, 
 
 __device__ __forceinline__ float exp_r(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504089f); }
 __device__ __forceinline__ double exp_r(double x) { return exp(x); }
+// e^x - 1 to full relative precision for small x (library functions)
+__device__ __forceinline__ float expm1_r(float x) { return expm1f(x); }
+__device__ __forceinline__ double expm1_r(double x) { return expm1(x); }
 __device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
 

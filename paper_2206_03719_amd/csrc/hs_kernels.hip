@@ -98,7 +98,7 @@ hipError_t launch_paths(bool fp32, int nmax, int scheme, int ft, const PathArgs&
         ((a.n - a.k_begin) % a.ck_every != 0 || (a.n - a.k_begin) / a.ck_every < 2))
         return hipErrorInvalidValue;
     // the block must fit the variant's launch bound
-    if (a.W < 1 || a.W > paths_max_waves(fp32, nmax)) return hipErrorInvalidValue;
+    if (a.W < 1 || a.W > paths_max_waves(fp32, scheme == HS_SCHEME_QE, nmax)) return hipErrorInvalidValue;
     if (!fp32)
         return scheme == HS_SCHEME_QE ? launch_paths_f64q(nmax, ft, a, nchunks, nbg, st)
                                       : launch_paths_f64e(nmax, ft, a, nchunks, nbg, st);

@@ -10,7 +10,7 @@ namespace hs {
 
 constexpr int kMaxAssets = 20;
 constexpr int kLanes = 64;        // one wave = 64 consecutive paths
-constexpr int kMaxWaves = 8;      // waves per path-kernel block
+constexpr int kMaxWaves = 16;     // most waves per path-kernel block (any variant)
 constexpr int kOwnPerWave = 4;    // base assets owned by one wave of a block
 constexpr int kGramThreads = 256; // Gram kernel block
 constexpr int kSweepThreads = 1024;
@@ -27,16 +27,19 @@ constexpr int paths_tmax_for(bool fp32, bool qe, int nmax)
                  : (nmax <= 8 ? 24 : nmax <= 12 ? 20 : nmax);
 }
 
-// Most waves per block of the Greek-set path kernel for a variant.  FP64 at
-// 13-16 assets needs more than 256 registers per lane; at one wave per SIMD
+// Most waves per block of the Greek-set path kernel for a variant: 16 for
+// FP32 Euler (at most 128 registers, which its tasks fit), so that all task
+// groups of a path chunk can share one block's random numbers and base
+// step; 8 otherwise.  FP64 at 13-16 assets needs more than 256 registers per
+// lane; at one wave per SIMD
 // (4 waves per block) the compiler holds the excess in the accumulation
 // registers instead of spilling it to memory (16 assets x 25k paths: 104 ->
 // 75 ms of path kernel, 13 assets: 60 -> 41 ms).  At 10 and 12 assets the
 // smaller spill costs less than the halved occupancy, and at 17-20 assets
 // the base assets need 5 waves.
-constexpr int paths_max_waves(bool fp32, int nmax)
+constexpr int paths_max_waves(bool fp32, bool qe, int nmax)
 {
-    return (!fp32 && nmax == 16) ? 4 : kMaxWaves;
+    return (fp32 && !qe) ? 16 : (!fp32 && nmax == 16) ? 4 : 8;
 }
 
 
@@ -72,7 +75,7 @@ struct BaseP {
     double L64[kMaxAssets * kMaxAssets];  // the same in FP64 (QE: FP64 spot normals)
     R S0_up[kMaxAssets];           // S0_i (1 + h) for the spot-up scenarios
     R S0_dn[kMaxAssets];           // S0_i (1 - h)
-    R r, dt, invN, pad;
+    R r, dt, invN, drdt;           // drdt: the rate scenario's (r' - r) dt
 };
 
 // A task advances one asset of one bumped scenario whose trajectory differs
@@ -105,7 +108,8 @@ struct GroupP {
     int32_t base_scen;  // feature plane of the base scenario, or -1
     int32_t spot_up0;   // plane of spot-up asset 0 (asset a at +a), or -1
     int32_t spot_dn0;   // plane of spot-down asset 0, or -1
-    int32_t pad[3];
+    int32_t rate_scen;  // plane of the rate scenario, or -1
+    int32_t pad[2];
 };
 
 // Base-scenario path kernel (features of the model alone, no Greek

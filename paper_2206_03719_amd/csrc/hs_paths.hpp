@@ -30,7 +30,7 @@ namespace {
 // normals eps, eta, Z^S and the variance state are FP64 (ZT, VT) in both
 // path precisions, so the variance path is the FP64 one.
 template <typename R, int NMAX, int TMAX, int SCHEME, typename FT, bool CK>
-__global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX))
+__global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEME == HS_SCHEME_QE, NMAX))
     k_paths(const PathArgs A)
 {
     using VT = std::conditional_t<SCHEME == HS_SCHEME_QE, double, R>;
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
     const int gidx = static_cast<int>(blockIdx.y) * W + w;
     const cptr<GroupP> gp = as_const<GroupP>(A.groups) + gidx;
     const int g_task0 = gp->task0, ntask = gp->ntask, g_base = gp->base_scen,
-              g_up0 = gp->spot_up0, g_dn0 = gp->spot_dn0;
+              g_up0 = gp->spot_up0, g_dn0 = gp->spot_dn0, g_rate = gp->rate_scen;
     const cptr<TaskP<R>> tk = as_const<TaskP<R>>(A.tasks) + g_task0;
 
     const R dt = bp->dt;
@@ -220,6 +220,17 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, NMAX)
                 f.u = static_cast<FT>(suf);
                 f.a = static_cast<FT>(bA);
                 feat[g_base * A.plane + off] = f;
+            }
+            if (g_rate >= 0) {
+                // the rate bump shifts every log price by (r' - r) t at date
+                // t = (k + 1) dt: U scales by e^{(r' - r) t}, A is the base's.
+                // U + U (e^x - 1): the small change keeps its full relative
+                // precision (the rate Greek is that change over the bump)
+                R2<FT> f;
+                f.u = static_cast<FT>(
+                    fma(suf, expm1_r(bp->drdt * static_cast<R>(k + 1)), suf));
+                f.a = static_cast<FT>(bA);
+                feat[g_rate * A.plane + off] = f;
             }
             if (g_up0 >= 0) {
                 // a spot bump rescales one asset of the base path; the other

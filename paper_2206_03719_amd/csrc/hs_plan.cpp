@@ -348,7 +348,7 @@ hs_status expand_scenarios(const Request& q, std::vector<Scenario>& out)
     }
     // own asset range: assets whose path differs from the base scenario's
     for (Scenario& s : out) {
-        if (s.kind <= 2) {
+        if (from_base_path(s.kind)) {
             s.lo = s.hi = 0;
             continue;
         }
@@ -552,6 +552,10 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
     }
     bp.r = static_cast<R>(q.r);
     bp.dt = static_cast<R>(q.opt.T / static_cast<double>(q.n));
+    // the rate scenario's log-price shift per step, (r' - r) dt
+    bp.drdt = R(0);
+    for (const Scenario& s : sc)
+        if (s.kind == 5) bp.drdt = static_cast<R>((s.r - q.r) * (q.opt.T / static_cast<double>(q.n)));
     bp.invN = static_cast<R>(1.0 / static_cast<double>(N));
     pp.base.resize(sizeof bp);
     std::memcpy(pp.base.data(), &bp, sizeof bp);
@@ -561,7 +565,7 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
     for (size_t i = 0; i < pass.scen.size(); ++i) plane[pass.scen[i]] = static_cast<int>(i);
 
     std::vector<TaskP<R>> tasks;
-    pp.groups.assign(static_cast<size_t>(pp.nbg) * pp.W, GroupP{0, 0, -1, -1, -1, {0, 0, 0}});
+    pp.groups.assign(static_cast<size_t>(pp.nbg) * pp.W, GroupP{0, 0, -1, -1, -1, -1, {0, 0}});
     for (size_t g = 0; g < group_scen.size(); ++g) {
         GroupP& G = pp.groups[g];
         G.task0 = static_cast<int32_t>(tasks.size());
@@ -571,6 +575,8 @@ void fill_tables(const Request& q, const Shape& sh, const std::vector<Scenario>&
                 G.spot_up0 = plane[1];
                 G.spot_dn0 = plane[1 + N];
             }
+            for (size_t si = 0; si < sc.size(); ++si)
+                if (sc[si].kind == 5) G.rate_scen = plane[si];
         }
         for (int si : group_scen[g]) {
             const Scenario& s = sc[si];
@@ -629,7 +635,7 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
     std::vector<int> units;
     int total = 0;
     for (int si : pass.scen)
-        if (sc[si].kind >= 3) {
+        if (!from_base_path(sc[si].kind)) {
             units.push_back(si);
             total += sc[si].hi - sc[si].lo;
         }
@@ -661,18 +667,19 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
         cnt[best] += w;
     }
     for (auto& v : gs) std::sort(v.begin(), v.end());
-    const int wcap = std::max(1, std::min(wmax > 0 ? wmax : kMaxWaves, kMaxWaves));
+    const int vmax = paths_max_waves(sh.fp32, q.opts.scheme == HS_SCHEME_QE, sh.nmax);
+    const int wcap = std::max(1, std::min(wmax > 0 ? wmax : vmax, vmax));
     int W = q.opts.waves_per_block > 0 ? q.opts.waves_per_block
                                        : std::min(static_cast<int>(gs.size()), wcap);
-    // more task groups than waves in a block: as few waves per block as the
+    // more task groups than a block holds: as few waves per block as the
     // base assets allow, unless that is 5 or more (measured on 8-20 assets
     // at 50k-200k paths: 3 or 4 waves per block run 30-42% faster than 8;
     // 5 and 6 run slower than 8)
     const int task_groups = (total + tmax - 1) / tmax;
-    if (q.opts.waves_per_block == 0 && wmax == 0 && task_groups > kMaxWaves)
-        W = wmin <= 4 ? wmin : kMaxWaves;
+    if (q.opts.waves_per_block == 0 && wmax == 0 && task_groups > vmax)
+        W = wmin <= 4 ? wmin : 8;
     W = std::max(W, wmin);
-    W = std::min(W, paths_max_waves(sh.fp32, sh.nmax));
+    W = std::min(W, vmax);
     pp.W = W;
     pp.nbg = static_cast<int>((gs.size() + W - 1) / W);
     // dates stored per scenario: all (American), a window of them, or the last
@@ -718,10 +725,10 @@ std::vector<Pass> make_passes(const Request& q, const Shape& sh, const std::vect
     std::vector<std::vector<int>> units;
     std::vector<int> head{0};
     for (size_t i = 1; i < sc.size(); ++i)
-        if (sc[i].kind <= 2) head.push_back(static_cast<int>(i));
+        if (from_base_path(sc[i].kind)) head.push_back(static_cast<int>(i));
     units.push_back(head);
     for (size_t i = 1; i < sc.size(); ++i)
-        if (sc[i].kind >= 3) units.push_back({static_cast<int>(i)});
+        if (!from_base_path(sc[i].kind)) units.push_back({static_cast<int>(i)});
     auto bytes_of = [&](int nscen, int ntask, int nunits, int window) {
         return layout_for(q, sh, nscen, ntask, nunits + 2 * kMaxWaves, window).total;
     };

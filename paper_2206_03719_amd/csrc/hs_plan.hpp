@@ -46,6 +46,13 @@ struct Scenario {
     int lo = 0, hi = 0;  // own asset range (assets whose path differs from base)
 };
 
+// Scenarios the path kernel derives from the base path without paths of
+// their own: the base, the spot bumps (one asset's prices rescaled) and the
+// rate bump (r enters the log price only through its drift r dt, so every
+// asset's log price moves by (r' - r) t and U by the factor e^{(r' - r) t},
+// while A and the variance paths stay the base's).
+inline bool from_base_path(int kind) { return kind <= 2 || kind == 5; }
+
 int basis_m(const Request& q);
 bool cholesky(int N, const std::vector<double>& C, std::vector<double>& L);
 hs_status expand_scenarios(const Request& q, std::vector<Scenario>& out);
