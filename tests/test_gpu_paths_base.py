@@ -91,18 +91,44 @@ def test_wide_fp32(N, P, n, draws):
     ref = oracle.features(w["model"], w["corr"], 1.0, n, P, 42)
     got = hs.path_features(w["model"], w["corr"], 1.0, P, n, seed=42,
                            precision="fp32").cpu().numpy().astype(np.float64)
-    check_fp32(got, ref, tight=draws == "feller")
+    tight = draws == "feller"
+    check_fp32(got, ref, tight, touched=None if tight else touched_zero(w, n, P))
 
 
-def check_fp32(got, ref, tight, u_bar=5e-5, q=0.99, q_bar=1e-6):
+def touched_zero(w, n, P, delta=1e-6):
+    """[n, P] mask: some asset's FP64 variance has come within delta of zero
+    at or before that date (the oracle's states date by date, on the same
+    Philox streams).  Where it has, the FP32 path may have truncated at a
+    different step than the FP64 one (full truncation takes max(v, 0))."""
+    hit = np.zeros((n, P), dtype=bool)
+    for k in range(1, n + 1):
+        v = oracle.states(w["model"], w["corr"], k / n, k, P, 42)[:, :, 1]
+        hit[k - 1] = (v <= delta).any(axis=1)
+    return np.logical_or.accumulate(hit, axis=0)
+
+
+def check_fp32(got, ref, tight, u_bar=5e-5, touched=None):
+    """U within u_bar relative everywhere; A within 5e-7 absolute element by
+    element wherever no asset's variance has touched zero (tight: nowhere
+    does), and within 1e-3 where one has.
+
+    The 5e-7 bar: A is a mean of N variances of size ~0.04 whose FP32 paths
+    carry about 1e-8 of accumulated rounding after a few hundred steps
+    (relative 6e-8 per operation, sqrt(n) growth); delta = 1e-6 of the
+    touched mask leaves that two orders of magnitude of room."""
     assert rel(got[..., 0], ref[..., 0]).max() <= u_bar
     ea = np.abs(got[..., 1] - ref[..., 1])
-    _say("  A error: quantile %.2f %.2e, max %.2e" % (q, np.quantile(ea, q), ea.max()))
     if tight:
+        _say("  A error: max %.2e" % ea.max())
         assert ea.max() <= 5e-7
-    else:
-        assert np.quantile(ea, q) <= q_bar
-        assert ea.max() <= 1e-3
+        return
+    clean = ea[~touched]
+    _say("  A error: untouched elements %d, max %.2e; touched %d, max %.2e"
+         % (clean.size, clean.max() if clean.size else 0.0, int(touched.sum()),
+            ea[touched].max() if touched.any() else 0.0))
+    assert clean.size > 0
+    assert clean.max() <= 5e-7
+    assert ea.max() <= 1e-3
 
 
 def test_wide_fp32_qe():
