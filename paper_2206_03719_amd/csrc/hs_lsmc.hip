@@ -697,19 +697,50 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
             // (2 Q scalar registers) alive across the whole loop
             int nl = nlive;
             asm volatile("" : "+v"(nl));
+            uint32_t exb = 0;  // bit i: path i exercised here
+            // four paths at a time, stage by stage, so that their FP64
+            // dependency chains interleave
+            constexpr int IL = 4;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                asm volatile("" : "+v"(f[i].u), "+v"(f[i].a));
-                const double U = static_cast<double>(f[i].u);
-                const double h = fmax(fma(U, sg, -sK), 0.0);
-                const double x = fma(U, A.inv_K, -bcU);
-                const double w = fma(static_cast<double>(f[i].a), iw, -bcA);
+            for (int i0 = 0; i0 < Q; i0 += IL) {
+                double U[IL], h[IL], x[IL], w[IL], t[IL], cont[IL];
+#pragma unroll
+                for (int j = 0; j < IL; ++j)
+                    if (i0 + j < Q) asm volatile("" : "+v"(f[i0 + j].u), "+v"(f[i0 + j].a));
+#pragma unroll
+                for (int j = 0; j < IL; ++j) {
+                    if (i0 + j >= Q) continue;
+                    U[j] = static_cast<double>(f[i0 + j].u);
+                    x[j] = fma(U[j], A.inv_K, -bcU);
+                    w[j] = fma(static_cast<double>(f[i0 + j].a), iw, -bcA);
+                }
+#pragma unroll
+                for (int j = 0; j < IL; ++j) {
+                    if (i0 + j >= Q) continue;
+                    h[j] = fmax(fma(U[j], sg, -sK), 0.0);
+                    t[j] = fma(beta[4], w[j], fma(beta[2], x[j], beta[1]));
+                }
                 // beta_0 + beta_1 x + beta_2 x^2 + beta_3 w + beta_4 x w
-                const double cont =
-                    fma(x, fma(beta[4], w, fma(beta[2], x, beta[1])), fma(beta[3], w, beta[0]));
-                const bool ex = i < nl && h > 0.0 && h > cont;
-                D[i] = ex ? h * d1 : D[i];
-                if (tau && ex) tau[i * kClusterThreads] = kd;
+#pragma unroll
+                for (int j = 0; j < IL; ++j)
+                    if (i0 + j < Q) cont[j] = fma(x[j], t[j], fma(beta[3], w[j], beta[0]));
+#pragma unroll
+                for (int j = 0; j < IL; ++j) {
+                    const int i = i0 + j;
+                    if (i >= Q) continue;
+                    // non-short-circuit: no branch around the continuation value
+                    const bool ex = (i < nl) & (h[j] > 0.0) & (h[j] > cont[j]);
+                    D[i] = ex ? h[j] * d1 : D[i];
+                    exb |= ex ? (1u << i) : 0u;
+                }
+            }
+            // exercise dates, only when exported: a store under a branch in
+            // the loop above would cut it into one block per path, and the
+            // compiler could no longer interleave the paths' FP64 chains
+            if (tau) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    if (exb & (1u << i)) tau[i * kClusterThreads] = kd;
             }
         };
 
@@ -735,20 +766,34 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
             double b[5] = {-0.0, -0.0, -0.0, -0.0, -0.0};
             if (ok) {
                 const double ik = idsc[k];
+                // four paths at a time, stage by stage (the sums still add
+                // the paths in order)
+                constexpr int IL = 4;
 #pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const double U = static_cast<double>(cur[i].u);
-                    const double x = fma(U, A.inv_K, -cU);
-                    const double w = fma(static_cast<double>(cur[i].a), iw, -cA);
-                    // paths out of the money add exact zeros, and so do paths
-                    // past P (their D stays 0: decide never exercises them)
-                    const double Y = fma(U, sg, -sK) > 0.0 ? D[i] * ik : 0.0;
-                    const double xY = x * Y;
-                    b[0] += Y;
-                    b[1] += xY;
-                    b[2] = fma(x, xY, b[2]);
-                    b[3] = fma(w, Y, b[3]);
-                    b[4] = fma(w, xY, b[4]);
+                for (int i0 = 0; i0 < Q; i0 += IL) {
+                    double x[IL], w[IL], Y[IL], xY[IL];
+#pragma unroll
+                    for (int j = 0; j < IL; ++j) {
+                        const int i = i0 + j;
+                        if (i >= Q) continue;
+                        const double U = static_cast<double>(cur[i].u);
+                        x[j] = fma(U, A.inv_K, -cU);
+                        w[j] = fma(static_cast<double>(cur[i].a), iw, -cA);
+                        // paths out of the money add exact zeros, and so do
+                        // paths past P (their D stays 0: decide never
+                        // exercises them)
+                        Y[j] = fma(U, sg, -sK) > 0.0 ? D[i] * ik : 0.0;
+                        xY[j] = x[j] * Y[j];
+                    }
+#pragma unroll
+                    for (int j = 0; j < IL; ++j) {
+                        if (i0 + j >= Q) continue;
+                        b[0] += Y[j];
+                        b[1] += xY[j];
+                        b[2] = fma(x[j], xY[j], b[2]);
+                        b[3] = fma(w[j], Y[j], b[3]);
+                        b[4] = fma(w[j], xY[j], b[4]);
+                    }
                 }
                 // the inverse factor's loads fly during the exchange
                 double Lk[15];
