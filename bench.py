@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--workload", choices=("bestof10", "bestof5"), default="bestof10")
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-slots", type=int, default=8,
+                    help="requests the serving loop runs at once")
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only the serving loop: --serve-requests (default 1000 here) requests "
                          "at offered loads 0.5, 0.8 and 0.95 of the saturated capacity")
@@ -313,7 +315,7 @@ def main():
         return
     if args.serve_sweep:
         n_req = args.serve_requests if "--serve-requests" in sys.argv else 1000
-        for line in serve_sweep(hs, torch, n_req):
+        for line in serve_sweep(hs, torch, n_req, args.serve_slots):
             print(json.dumps(line), flush=True)
         return
     graph = not args.no_graph
@@ -398,7 +400,7 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_serve:
-        out["latency"] = serve_leg(hs, torch, args.serve_requests, 0.8)
+        out["latency"] = serve_leg(hs, torch, args.serve_requests, 0.8, args.serve_slots)
         log("serving: %s" % json.dumps(out["latency"]))
 
     print(json.dumps(out), flush=True)
@@ -550,18 +552,18 @@ def _poisson_run(hs, srv, n_req, rate, seed):
             "max_ms": float(lat.max()), "seconds": t_run}
 
 
-def _server(hs, torch, slots=4):
+def _server(hs, torch, slots=8):
     free, total = torch.cuda.mem_get_info()
     pool = int(min(free * 0.7, 160e9))
     return hs.Server(pool, max_slots=slots), pool
 
 
-def serve_leg(hs, torch, n_req, load):
+def serve_leg(hs, torch, n_req, load, slots=8):
     """Poisson stream of mixed-size full-Greek-set requests (assets U{1..20},
     paths U[10k, 400k], steps U{52,126,252,504}) through the serving loop.
     First the saturated capacity (all requests queued at once), then a
     Poisson stream at `load` of it: p50/p99 latency from submit to result."""
-    srv, pool = _server(hs, torch)
+    srv, pool = _server(hs, torch, slots)
     try:
         cap, sat_steps = _saturated(hs, srv, n_req)
         run = _poisson_run(hs, srv, n_req, load * cap, seed=12)
@@ -575,10 +577,10 @@ def serve_leg(hs, torch, n_req, load):
         srv.close()
 
 
-def serve_sweep(hs, torch, n_req):
+def serve_sweep(hs, torch, n_req, slots=8):
     """The serving loop at offered loads 0.5, 0.8 and 0.95 of its saturated
     capacity, n_req requests each: one JSON line per load."""
-    srv, pool = _server(hs, torch)
+    srv, pool = _server(hs, torch, slots)
     try:
         log("serve sweep: saturated capacity over %d requests" % n_req)
         cap, sat_steps = _saturated(hs, srv, n_req)

@@ -339,9 +339,10 @@ hs_status hs_normals(uint64_t seed, int32_t n_assets, int64_t n_paths, int32_t n
 /* ---------------------------------------------------------------------------
  * Serving: a continuous-batching request loop (an interface of this library;
  * the paper times single runs).  A server owns a caller-provided device pool
- * (its size is the HBM budget).  An idle slot admits the first queued request
- * whose workspace fits the free pool, so a small request may pass a large
- * one waiting for memory; the head of the queue is passed at most
+ * (its size is the HBM budget).  An idle slot admits, among the queued
+ * requests whose workspace fits the free pool, the one with the least
+ * estimated work (path-steps x (scenarios + path tasks)), so small requests
+ * do not wait behind large ones; a request is passed by later ones at most
  * 2 x max_slots times, after which the slots wait for it.  Admitted requests
  * run on their own HIP streams: their path and Gram kernels run side by side
  * on the device, and a backward sweep whose workgroups wait on each other

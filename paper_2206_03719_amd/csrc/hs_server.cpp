@@ -1,10 +1,10 @@
 // hs_server.cpp -- continuous-batching request loop.
 //
 // The server owns a caller-provided device pool (the HBM budget).  Requests
-// queue in arrival order; an idle slot admits the first queued request whose
-// workspace fits the free pool (first fit), so a small request may pass a
-// large one that is waiting for memory -- but a request at the head of the
-// queue is passed at most 2 x slots times, after which the slots wait for it.
+// queue in arrival order; an idle slot admits, among the queued requests
+// whose workspace fits the free pool, the one with the least estimated work,
+// so small requests do not wait behind large ones -- but a request is passed
+// at most 2 x slots times, after which the slots wait for it.
 // Requests that arrive while others run start as slots and memory free up.
 // Every slot is a host worker thread with its own HIP stream (default
 // priority).  The path and Gram kernels of admitted requests run side by side
@@ -77,6 +77,12 @@ public:
             }
         }
     }
+    size_t largest_free() const
+    {
+        size_t m = 0;
+        for (const auto& f : free_) m = std::max(m, f.second);
+        return m;
+    }
     size_t used() const { return used_; }
     size_t peak() const { return peak_; }
     size_t size() const { return size_; }
@@ -92,12 +98,14 @@ struct Item {
     uint64_t ticket = 0;
     Request q;
     size_t ws = 0;
+    size_t ws_min = 0;  // the least workspace it runs in (more passes)
     St state = St::Queued;
     hs_status status = HS_OK;
     std::string error;
     RunResult res;
     Clock::time_point t_submit, t_done;
     int passed = 0;  // admissions of later requests while this one was queued
+    double work = 0.0;  // estimated device work: path-steps x (scenarios + path tasks)
 };
 
 // Times (seconds) a request's work was on the device, from the reference event.
@@ -130,19 +138,34 @@ struct hs_server {
 namespace hs {
 namespace {
 
-// First fit over the queue (caller holds s->mu): the first queued request
-// whose workspace the free pool holds, reserving it at *off.  The head may be
-// passed at most 2 x slots times; after that only the head is admitted.
+// Admission (caller holds s->mu): the queued request with the least
+// estimated work whose workspace the free pool holds, reserving it at *off;
+// every older request it passes counts one more pass.  A request passed
+// 2 x slots times goes next: the oldest such request is admitted as soon as
+// the pool holds it, and nothing passes it meanwhile (bounded waiting).
 std::deque<Item*>::iterator admit(hs_server* s, size_t* off)
 {
     auto& q = s->queue;
-    for (auto it = q.begin(); it != q.end(); ++it) {
+    const int limit = 2 * s->max_slots;
+    for (auto it = q.begin(); it != q.end(); ++it)
+        if ((*it)->passed >= limit) {
+            // it may shrink to the largest free block (at least its minimum):
+            // it runs in more passes, with the same results, instead of
+            // holding every slot until its full workspace frees up
+            const size_t fb = s->alloc.largest_free() & ~size_t(255);
+            if (fb < (*it)->ws && fb >= (*it)->ws_min) (*it)->ws = fb;
+            return s->alloc.alloc((*it)->ws, off) ? it : q.end();
+        }
+    std::vector<std::deque<Item*>::iterator> order;
+    order.reserve(q.size());
+    for (auto it = q.begin(); it != q.end(); ++it) order.push_back(it);
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto& a, const auto& b) { return (*a)->work < (*b)->work; });
+    for (auto it : order)
         if (s->alloc.alloc((*it)->ws, off)) {
-            if (it != q.begin()) ++q.front()->passed;
+            for (auto o = q.begin(); o != it; ++o) ++(*o)->passed;
             return it;
         }
-        if (it == q.begin() && (*it)->passed >= 2 * s->max_slots) break;
-    }
     return q.end();
 }
 
@@ -294,6 +317,11 @@ hs_status hs_submit(hs_server* s, const hs_request* r, uint64_t* ticket)
         std::vector<Scenario> sc;  // catches non-SPD bumped correlations now
         rc = expand_scenarios(it->q, sc);
         if (rc != HS_OK) return rc;
+        // work estimate for admission order: every scenario's sweep and
+        // Gram reads, and the base path and every path task
+        double units = static_cast<double>(sc.size() + it->q.N);
+        for (const Scenario& x : sc) units += x.hi - x.lo;
+        it->work = units * static_cast<double>(it->q.P) * static_cast<double>(it->q.n);
     }
     const size_t full = workspace_bound(it->q, false);
     const size_t mn = workspace_bound(it->q, true);
@@ -306,6 +334,7 @@ hs_status hs_submit(hs_server* s, const hs_request* r, uint64_t* ticket)
     // minimum), so that it leaves room for others; results do not depend on
     // the workspace size
     it->ws = full <= cap ? full : std::max(mn, cap / 2);
+    it->ws_min = mn;
     it->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);

@@ -1,5 +1,5 @@
-"""Serving loop on the GPU: continuous batching by HBM budget with first-fit
-admission, overlap of requests on the device (their device intervals from HIP
+"""Serving loop on the GPU: continuous batching by HBM budget with
+least-work-first admission among the requests that fit, overlap of requests on the device (their device intervals from HIP
 events intersect), and each request's result bit-identical alone and in a
 mix of uneven requests."""
 import sys
@@ -116,7 +116,7 @@ def test_budget_admission_and_overlap():
     assert st["device_overlap_s"] > 0.0
 
 
-def test_first_fit_admission_passes_a_waiting_request():
+def test_admission_passes_a_waiting_request():
     # A takes most of the pool; B (as large) waits at the head of the queue;
     # C (small) fits beside A and is admitted past B, so it finishes first
     import paper_2206_03719_amd as hs
@@ -180,3 +180,31 @@ def test_cancel_and_errors():
         srv.submit(big)
     assert e.value.status == hs.ENOMEM
     srv.close()
+
+
+def test_small_requests_pass_large_ones_within_the_bound():
+    # one slot: a queue of large requests with a small one behind them; the
+    # small one (least work) is admitted as soon as the slot frees, ahead of
+    # the queued large ones, and every request completes (the pass bound
+    # keeps the large ones from waiting for ever)
+    import paper_2206_03719_amd as hs
+    big = W.best_of_call(n_assets=8, n_paths=100000, n_steps=126)  # ~10 ms each
+    small = W.best_of_call(n_assets=2, n_paths=2000, n_steps=26)
+    srv = hs.Server(24 << 30, max_slots=1)
+    tb = [srv.submit(big) for _ in range(3)]
+    ts = srv.submit(small)  # queued behind two large ones while the first runs
+    order = []
+    t0 = time.time()
+    pending = set(tb) | {ts}
+    while pending:
+        for t in list(pending):
+            if srv.poll(t) is not None:
+                order.append(t)
+                pending.discard(t)
+        assert time.time() - t0 < 120
+        time.sleep(0.0005)
+    st = srv.stats()
+    srv.close()
+    _say("  completion order: %s (small %d)" % (order, ts))
+    assert st["completed"] == 4
+    assert order.index(ts) <= 1  # only the request already running finishes before it
