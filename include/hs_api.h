@@ -166,8 +166,10 @@ typedef struct hs_bumps {
 typedef struct hs_opts {
     int32_t precision;       /* HS_FP64 | HS_FP32_PATHS                          */
     int32_t waves_per_block; /* path kernel launch shape: 0 = the tuned or
-                                planner's choice, else 1..8 waves per block (FP64 at
-                                13-16 assets runs at most 4).  A block always follows
+                                planner's choice, else 1..16 waves per block (capped
+                                at the variant's most: 16 for FP32 Euler, 8 else, 4
+                                for FP64 at 13-16 assets, FP64 QE from 10 and FP64
+                                or QE at 17-20).  A block always follows
                                 64 paths (one per lane) through every step; its waves
                                 split the scenario groups, so this is the library's
                                 paths-per-block and work-per-wave knob.  Steps are

@@ -88,6 +88,13 @@ __device__ __forceinline__ void box_muller(uint32_t w1, uint32_t w2, double& e, 
 
 __device__ __forceinline__ float exp_r(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504089f); }
 __device__ __forceinline__ double exp_r(double x) { return exp(x); }
+// max(x, 0) for a finite x: one v_med3 in FP32 (a compare-select there
+// became a quieting max plus a max)
+__device__ __forceinline__ float pos_r(float x)
+{
+    return __builtin_amdgcn_fmed3f(x, 0.0f, __builtin_huge_valf());
+}
+__device__ __forceinline__ double pos_r(double x) { return x > 0.0 ? x : 0.0; }
 // e^x - 1 to full relative precision for small x (library functions)
 __device__ __forceinline__ float expm1_r(float x) { return expm1f(x); }
 __device__ __forceinline__ double expm1_r(double x) { return expm1(x); }

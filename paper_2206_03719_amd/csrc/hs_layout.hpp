@@ -12,6 +12,9 @@ constexpr int kMaxAssets = 20;
 constexpr int kLanes = 64;        // one wave = 64 consecutive paths
 constexpr int kMaxWaves = 16;     // most waves per path-kernel block (any variant)
 constexpr int kOwnPerWave = 4;    // base assets owned by one wave of a block
+// ... in the asset bucket nmax: 5 in the 20-asset bucket, so that four
+// waves (one per SIMD) own its base assets
+constexpr int paths_own_per_wave(int nmax) { return nmax > 16 ? 5 : kOwnPerWave; }
 constexpr int kGramThreads = 256; // Gram kernel block
 constexpr int kSweepThreads = 1024;
 constexpr int kRegRec = 20;       // doubles per (scenario, date) regression record
@@ -35,11 +38,14 @@ constexpr int paths_tmax_for(bool fp32, bool qe, int nmax)
 // (4 waves per block) the compiler holds the excess in the accumulation
 // registers instead of spilling it to memory (16 assets x 25k paths: 104 ->
 // 75 ms of path kernel, 13 assets: 60 -> 41 ms).  At 10 and 12 assets the
-// smaller spill costs less than the halved occupancy, and at 17-20 assets
-// the base assets need 5 waves.
+// smaller spill costs less than the halved occupancy.  The 20-asset FP64
+// and QE variants (20 tasks of FP64 state per wave) and FP64 QE from 10
+// assets take the same bound (the 20-asset bucket with five base assets per
+// wave), so that no variant spills.
 constexpr int paths_max_waves(bool fp32, bool qe, int nmax)
 {
-    return (fp32 && !qe) ? 16 : (!fp32 && nmax == 16) ? 4 : 8;
+    return (fp32 && !qe) ? 16
+           : ((!fp32 && nmax == 16) || (!fp32 && qe && nmax >= 10) || nmax == 20) ? 4 : 8;
 }
 
 

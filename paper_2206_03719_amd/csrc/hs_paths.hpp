@@ -80,10 +80,11 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
     const int nblk = (N + 1) / 2;
 
     // base assets owned by this wave: a = w + i W
-    R Xo[kOwnPerWave];
-    VT Vo[kOwnPerWave];
+    constexpr int OWN = paths_own_per_wave(NMAX);
+    R Xo[OWN];
+    VT Vo[OWN];
 #pragma unroll
-    for (int i = 0; i < kOwnPerWave; ++i) {
+    for (int i = 0; i < OWN; ++i) {
         const int a = w + i * W;
         Xo[i] = R(0);
         Vo[i] = (a < N) ? static_cast<VT>(SCHEME == HS_SCHEME_QE ? bp->a[a].qe.v0 : bp->a[a].v0)
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
         const R* const bx = static_cast<const R*>(A.ckx) + row0 * P + p;
         const VT* const bv = static_cast<const VT*>(A.ckv) + row0 * P + p;
 #pragma unroll
-        for (int i = 0; i < kOwnPerWave; ++i) {
+        for (int i = 0; i < OWN; ++i) {
             const int a = w + i * W;
             if (a < N) {
                 Xo[i] = bx[static_cast<int64_t>(a) * P];
@@ -150,7 +151,7 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
 
         // 2) the base scenario's owned assets: Z^S = L eps, then the time step
 #pragma unroll
-        for (int i = 0; i < kOwnPerWave; ++i) {
+        for (int i = 0; i < OWN; ++i) {
             const int a = w + i * W;
             if (a < N) {
                 ZT z = ZT(0);
@@ -160,14 +161,14 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
                     qe_step(&q->qe, z, s_eta[a * kLanes + lane], Xo[i], Vo[i]);
                 } else {
                     const R zv = q->rho * z + q->rhobar * s_eta[a * kLanes + lane];
-                    const R vp = Vo[i] > R(0) ? Vo[i] : R(0);
+                    const R vp = pos_r(Vo[i]);
                     const R sq = sqrt_r(vp * dt);
                     Xo[i] = Xo[i] + (r - half * vp) * dt + sq * z;
                     Vo[i] = Vo[i] + q->kappa * (q->theta - vp) * dt + q->xi * sq * zv;
                 }
                 s_zs[a * kLanes + lane] = z;
                 s_e[a * kLanes + lane] = exp_r(Xo[i]);
-                s_vp[a * kLanes + lane] = static_cast<R>(Vo[i] > VT(0) ? Vo[i] : VT(0));
+                s_vp[a * kLanes + lane] = static_cast<R>(pos_r(Vo[i]));
             }
         }
         __syncthreads();
@@ -282,25 +283,25 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
 #pragma unroll
                     for (int b = 0; b < NMAX; ++b) z += T->L[b] * eps[b];
                     const R zv = T->rho * z + T->rhobar * s_eta[a_el + lane];
-                    const R vp = tV[t] > R(0) ? tV[t] : R(0);
+                    const R vp = pos_r(tV[t]);
                     const R sq = sqrt_r(vp * T->dt);
                     tX[t] = tX[t] + (T->r - half * vp) * T->dt + sq * z;
                     tV[t] = tV[t] + T->kappa * (T->theta - vp) * T->dt + T->xi * sq * zv;
                 }
                 const R S = T->S0 * exp_r(tX[t]);
-                const R vpt = static_cast<R>(tV[t] > VT(0) ? tV[t] : VT(0));
+                const R vpt = static_cast<R>(pos_r(tV[t]));
                 const R m0 = lds_get(s_pmx + lo_el + lane);
                 const R s0 = lds_get(s_psx + lo_el + lane);
-                const R tail = lds_get(s_smx + hi_el + lane);
-                const R ptail = lds_get(s_psx + N * kLanes + lane) - lds_get(s_psx + hi_el + lane);
                 const bool first = (flags & 1) != 0;
                 runM = first ? m0 : runM;
                 runS = first ? s0 : runS;
                 runM = S > runM ? S : runM;
                 runS = runS + vpt;
                 if (flags & 2) {
+                    const R tail = lds_get(s_smx + hi_el + lane);
                     runM = tail > runM ? tail : runM;
-                    runS = runS + ptail;
+                    runS = runS + (lds_get(s_psx + N * kLanes + lane) -
+                                   lds_get(s_psx + hi_el + lane));
                     if (store && live) {
                         R2<FT> f;
                         f.u = static_cast<FT>(runM);
@@ -321,7 +322,7 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
             VT* const bv = static_cast<VT*>(A.ckv) + row0 * P + p;
             if (blockIdx.y == 0) {
 #pragma unroll
-                for (int i = 0; i < kOwnPerWave; ++i) {
+                for (int i = 0; i < OWN; ++i) {
                     const int a = w + i * W;
                     if (a < N) {
                         bx[static_cast<int64_t>(a) * P] = Xo[i];

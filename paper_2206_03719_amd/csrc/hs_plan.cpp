@@ -643,7 +643,8 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
         return (sc[a].hi - sc[a].lo) > (sc[b].hi - sc[b].lo);
     });
     const int tmax = sh.tmax;
-    const int wmin = (N + kOwnPerWave - 1) / kOwnPerWave;
+    const int own = paths_own_per_wave(sh.nmax);
+    const int wmin = (N + own - 1) / own;
     int G = std::max(1, (total + tmax - 1) / tmax);
     const int desired = (target_waves + pp.nchunks - 1) / pp.nchunks;
     G = std::max(G, std::min(desired, static_cast<int>(units.size()) + 1));

@@ -86,7 +86,7 @@ def _call(w, ws_bytes=1 << 34, workspace=FAKE_WS, corr=None, n_paths=None, n_ste
     (dict(bumps__T_abs=2.0), hs.EINVAL),
     (dict(bumps__mask=64), hs.EINVAL),
     (dict(opts__precision=3), hs.EINVAL),
-    (dict(opts__waves_per_block=9), hs.EINVAL),
+    (dict(opts__waves_per_block=17), hs.EINVAL),
     (dict(opts__sweep_mode=1, n_paths=200000), hs.EINVAL),
     (dict(ws_bytes=4096), hs.ENOMEM),
 ])
@@ -182,9 +182,9 @@ def test_path_features_validation():
     assert _features_call(0)[0] == hs.EINVAL
     st, msg = _features_call(21, flags=hs.FLAG_GREEK_SET_KERNEL)
     assert st == hs.EINVAL and "1..20" in msg
-    # waves: 0..16 (0..8 with the Greek-set kernel); unknown flags rejected
+    # waves: 0..16 (also with the Greek-set kernel); unknown flags rejected
     assert _features_call(64, wpb=17)[0] == hs.EINVAL
-    assert _features_call(20, wpb=9, flags=hs.FLAG_GREEK_SET_KERNEL)[0] == hs.EINVAL
+    assert _features_call(20, wpb=17, flags=hs.FLAG_GREEK_SET_KERNEL)[0] == hs.EINVAL
     assert _features_call(20, flags=16)[0] == hs.EINVAL
     assert _features_call(20, n_paths=(1 << 31) + 1)[0] == hs.EINVAL
     # valid requests fail only on the sizes
