@@ -260,9 +260,13 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
         //    path); a scenario's own assets [lo, hi) are consecutive tasks,
         //    joined to the base's assets outside them through the prefix tables
         R runM = R(0), runS = R(0);
+        // the task count, opaque here: the compiler compares t < nt at each
+        // task instead of keeping TMAX masks in (spilled) scalar registers
+        int nt = ntask;
+        asm volatile("" : "+s"(nt));
 #pragma unroll
         for (int t = 0; t < TMAX; ++t) {
-            if (t < ntask) {
+            if (t < nt) {
                 const cptr<TaskP<R>> T = tk + t;
                 // the Euler step's constants lead the record: a few wide
                 // scalar loads
@@ -290,11 +294,10 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
                 }
                 const R S = T->S0 * exp_r(tX[t]);
                 const R vpt = static_cast<R>(pos_r(tV[t]));
-                const R m0 = lds_get(s_pmx + lo_el + lane);
-                const R s0 = lds_get(s_psx + lo_el + lane);
-                const bool first = (flags & 1) != 0;
-                runM = first ? m0 : runM;
-                runS = first ? s0 : runS;
+                if (flags & 1) {  // a scenario's first task: the base assets below lo
+                    runM = lds_get(s_pmx + lo_el + lane);
+                    runS = lds_get(s_psx + lo_el + lane);
+                }
                 runM = S > runM ? S : runM;
                 runS = runS + vpt;
                 if (flags & 2) {
