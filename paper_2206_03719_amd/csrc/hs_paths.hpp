@@ -53,7 +53,8 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
     const int lane = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int W = A.W;
-    const int N = A.N;
+    const int N0 = A.N;
+    const int N = N0;
     const int64_t p = static_cast<int64_t>(blockIdx.x) * kLanes + lane;
     const bool live = p < A.P;
 
@@ -128,6 +129,11 @@ __global__ void __launch_bounds__(kLanes * paths_max_waves(sizeof(R) == 4, SCHEM
     }
 
     for (int k = CK ? A.k_begin : 0; k < (CK ? A.k_end : A.n); ++k) {
+        // the asset count (shadowing the kernel's), opaque here: the compiler
+        // compares a < N where needed instead of keeping per-asset masks in
+        // (spilled) scalar registers across the step loop
+        int N = N0;
+        asm volatile("" : "+s"(N));
         unsigned char* const pb = hs_smem + (k & 1) * PAR;
         ZT* const s_eps = reinterpret_cast<ZT*>(pb);
         VT* const s_eta = reinterpret_cast<VT*>(pb + SZ);
