@@ -274,6 +274,22 @@ def test_sweep_variants_vs_oracle(P):
         assert np.array_equal(g["tau"], o["tau"]), sm
 
 
+@pytest.mark.parametrize("N,mask,P", [(3, 1, 25000), (2, 2, 7001), (5, 31, 3000)])
+def test_cluster_sweep_scenarios_vs_oracle(N, mask, P):
+    # the cluster sweep over several scenarios per launch (7, 3 and 28), the
+    # last workgroup of each scenario ragged; FP64 paths, so the exercise
+    # dates are the oracle's
+    w = W.best_of_call(n_assets=N, n_paths=P, n_steps=40, mask=mask)
+    S = oracle.num_scenarios(N, mask)
+    _say("cluster sweep N=%d mask=%d P=%d (%d scenarios)" % (N, mask, P, S))
+    o = orc(w, export_tau=True)
+    g = gpu(w, "fp64", export_tau=True)
+    assert rel(g["scenario_price"], o["scenario_price"]).max() <= 1e-12
+    assert rel(g["scenario_se"], o["scenario_se"]).max() <= 1e-9
+    assert g["skipped_regressions"] == int(o["skipped"].sum())
+    assert np.array_equal(g["tau"], o["tau"])
+
+
 def test_repeat_runs_identical():
     w = W.best_of_call(n_assets=4, n_paths=5000, n_steps=30)
     a = gpu(w, "fp32")
