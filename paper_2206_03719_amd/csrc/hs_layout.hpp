@@ -222,16 +222,20 @@ constexpr int kMaxClusterGroups = 1024;
 constexpr int kPlanComputeUnits = 256;  // MI355X: the cluster sweep plans for this many CUs
 // Paths per thread of the cluster sweep: the counts it is compiled for, and
 // the most a workgroup holds in registers (two dates of features and the
-// discounted cash flow per path, with the compiler's temporaries about 11
-// registers per path with 8-byte features, FP32 pairs, and 15 with FP64
-// pairs; up to 6 paths per thread two workgroups share a CU, above that one
-// workgroup per CU with up to 256 registers, which holds 16 (FP64 pairs: 12)
-// without spilling; 16-bit pairs spill at 16).
+// discounted cash flow per path, with the compiler's temporaries about 9
+// registers per path with 8-byte features, FP32 pairs, and 17 with FP64
+// pairs; up to 6 paths per thread (FP64 pairs: 5) two workgroups share a CU,
+// above that one workgroup per CU with up to 256 registers, which holds 22
+// FP32 pairs (250 registers; 24 spill) and 12 FP64 pairs without spilling).
+// More paths per thread mean fewer workgroups per scenario, so more
+// scenarios per launch and fewer launches of a large Greek set, each a chain
+// of exchanges.
 constexpr bool cluster_q_supported(int q, int ft)
 {
-    return (q >= 1 && q <= 8) || q == 10 || q == 12 || (ft == kFeatF32 && q == 16);
+    return (q >= 1 && q <= 8) || q == 10 || q == 12 ||
+           (ft == kFeatF32 && (q == 16 || q == 18 || q == 20 || q == 22));
 }
-constexpr int cluster_qmax(int ft) { return ft == kFeatF32 ? 16 : 12; }
+constexpr int cluster_qmax(int ft) { return ft == kFeatF32 ? 22 : 12; }
 
 // Partial slots start as kEmptySlot (a NaN bit pattern that arithmetic never
 // produces); a workgroup's published partial is the slot's only write.

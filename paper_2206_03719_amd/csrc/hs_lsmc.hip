@@ -320,6 +320,14 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
     for (int j = threadIdx.x; j <= n; j += kSweepThreads) sdisc[j] = A.disc[static_cast<int64_t>(s) * (n + 1) + j];
     __syncthreads();
 
+    // the thread index, opaque at each use: the compiler forms a path's index
+    // and address where it needs them instead of keeping Q of them in
+    // registers across the date loop
+    auto tx = []() {
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        return t;
+    };
     double* const gcf = GLB ? A.cf + static_cast<int64_t>(s) * P : nullptr;
     int32_t* const gtau = GLB ? A.tau + static_cast<int64_t>(s) * P : nullptr;
     const int64_t last = static_cast<int64_t>(n - A.f_date0) * P;  // date n
@@ -330,7 +338,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
     if (!GLB) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const int64_t p = threadIdx.x + static_cast<int64_t>(i) * kSweepThreads;
+            const int64_t p = tx() + static_cast<int64_t>(i) * kSweepThreads;
             cf[i] = p < P ? payoff(A.cp, A.K, static_cast<double>(F[last + p].u)) : 0.0;
             tau[i] = n;
         }
@@ -356,7 +364,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
             if (!GLB) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const int64_t p = threadIdx.x + static_cast<int64_t>(i) * kSweepThreads;
+                    const int64_t p = tx() + static_cast<int64_t>(i) * kSweepThreads;
                     if (p < P) {
                         const R2<R> f = Fk[p];
                         const double U = static_cast<double>(f.u);
@@ -393,7 +401,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
             if (!GLB) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const int64_t p = threadIdx.x + static_cast<int64_t>(i) * kSweepThreads;
+                    const int64_t p = tx() + static_cast<int64_t>(i) * kSweepThreads;
                     if (p < P) {
                         const R2<R> f = Fk[p];
                         const double U = static_cast<double>(f.u);
@@ -445,7 +453,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
     if (!GLB) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const int64_t p = threadIdx.x + static_cast<int64_t>(i) * kSweepThreads;
+            const int64_t p = tx() + static_cast<int64_t>(i) * kSweepThreads;
             if (p < P) s1[0] += cf[i] * sdisc[tau[i]];
         }
     } else {
@@ -457,7 +465,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(const LsmcArgs A)
     if (!GLB) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const int64_t p = threadIdx.x + static_cast<int64_t>(i) * kSweepThreads;
+            const int64_t p = tx() + static_cast<int64_t>(i) * kSweepThreads;
             if (p < P) {
                 const double d = cf[i] * sdisc[tau[i]] - mean;
                 s2[0] += d * d;
@@ -580,12 +588,13 @@ __device__ __forceinline__ bool cluster_exchange(double (&b)[K], int m, double* 
 // k's exchange, so they fly during it (the exchange's polls complete after
 // them: vector loads of a wave complete in order), and nothing waits for them
 // until date k - 1.  The loop is unrolled twice so that the two buffers swap
-// roles by renaming.  Up to 6 paths per thread two workgroups share a CU
-// (4 waves per SIMD, 128 registers); more paths per thread (large Greek sets:
-// fewer launches, each a chain of exchanges) take one workgroup per CU and up
-// to 256 registers.
+// roles by renaming.  Up to 6 paths per thread (5 with FP64 features, whose
+// two dates take 8 registers per path) two workgroups share a CU (4 waves per
+// SIMD, 128 registers); more paths per thread (large Greek sets: fewer
+// launches, each a chain of exchanges) take one workgroup per CU and up to
+// 256 registers.
 template <typename R, int Q, bool WIN>
-__global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
+__global__ void __launch_bounds__(kClusterThreads, Q <= (sizeof(R) == 8 ? 5 : 6) ? 4 : 2)
     k_sweep_cluster(const LsmcArgs A, const ClusterArgs C)
 {
     extern __shared__ unsigned char hs_smem[];
@@ -632,13 +641,18 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
     // chunk's paths of that date: the whole offset is in the lane's offset,
     // which the buffer unit range-checks, so paths past the chunk read 0
     // (never used) instead of memory past the plane
+    // The lane offsets of a date's Q loads are formed afresh at each load from
+    // an opaque base (one add each) instead of being kept in Q registers
+    // across the sweep.
     const uint32_t voff = static_cast<uint32_t>(tid) * sizeof(R2<R>);
     auto load = [&](int k, R2<R>(&buf)[Q]) {
         const auto rs = buffer_over(F + static_cast<int64_t>(k - f0) * P,
                                     static_cast<uint32_t>(chunk) * sizeof(R2<R>));
+        uint32_t vo = voff;
+        asm volatile("" : "+v"(vo));
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            buf[i] = buffer_load<R2<R>>(rs, voff + i * kClusterThreads * sizeof(R2<R>), 0);
+            buf[i] = buffer_load<R2<R>>(rs, vo + i * kClusterThreads * sizeof(R2<R>), 0);
     };
 
     // State per path: the cash flow discounted to time 0, D = h_tau exp(-r tau
@@ -647,7 +661,14 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
     // date tau, wanted only for export, goes straight to memory at each
     // exercise (the sweep runs backward, so the last write is the earliest
     // exercise date).
-    int32_t* const tau = A.export_tau ? A.tau + static_cast<int64_t>(s) * P + pbase + tid : nullptr;
+    // (the chunk's base; each store forms its lane's address afresh from an
+    // opaque thread index, so that no per-path addresses stay alive)
+    int32_t* const tau = A.export_tau ? A.tau + static_cast<int64_t>(s) * P + pbase : nullptr;
+    auto put_tau = [&](int i, int v) {
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        tau[t + i * kClusterThreads] = v;
+    };
     double D[Q];
     if (!WIN || A.win_first) {
         R2<R> fn[Q];
@@ -659,7 +680,7 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             D[i] = i < nlive ? payoff(A.cp, A.K, static_cast<double>(fn[i].u)) * dn : 0.0;
-            if (tau && i < nlive) tau[i * kClusterThreads] = n;
+            if (tau && i < nlive) put_tau(i, n);
         }
     } else {
         const double* const dstate = A.cf + static_cast<int64_t>(s) * P + pbase + tid;
@@ -740,7 +761,7 @@ __global__ void __launch_bounds__(kClusterThreads, Q <= 6 ? 4 : 2)
             if (tau) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
-                    if (exb & (1u << i)) tau[i * kClusterThreads] = kd;
+                    if (exb & (1u << i)) put_tau(i, kd);
             }
         };
 
@@ -931,16 +952,31 @@ int cluster_capacity_t(size_t lds)
     return per_cu * cus;
 }
 
-// Calls f with the paths-per-thread count q as a compile-time constant (the
-// counts cluster_q_supported admits).
-template <typename Ret, typename Fn>
+// The feature storage code of a feature type.
+template <typename FT>
+constexpr int feat_code()
+{
+    return std::is_same_v<FT, float>      ? kFeatF32
+           : std::is_same_v<FT, double>   ? kFeatF64
+           : std::is_same_v<FT, _Float16> ? kFeatF16
+                                          : kFeatBF16;
+}
+
+// Calls f with the paths-per-thread count q as a compile-time constant, for
+// the counts cluster_q_supported admits with features FT (others return bad
+// and are never instantiated).
+template <typename FT, typename Ret, typename Fn>
 Ret with_q(int q, Ret bad, Fn&& f)
 {
     switch (q) {
-#define HS_Q(Q) \
-    case Q: return f(std::integral_constant<int, Q>{});
+#define HS_Q(Q)                                                        \
+    case Q:                                                            \
+        if constexpr (cluster_q_supported(Q, feat_code<FT>()))         \
+            return f(std::integral_constant<int, Q>{});                \
+        else                                                           \
+            return bad;
         HS_Q(1) HS_Q(2) HS_Q(3) HS_Q(4) HS_Q(5) HS_Q(6) HS_Q(7) HS_Q(8) HS_Q(10) HS_Q(12)
-        HS_Q(16)
+        HS_Q(16) HS_Q(18) HS_Q(20) HS_Q(22)
 #undef HS_Q
     default: return bad;
     }
@@ -960,7 +996,7 @@ int cluster_capacity(int ft, int q, bool win, size_t lds)
     if (!cluster_q_supported(q, ft)) return 0;
     return with_feat(ft, 0, [&](auto tag) -> int {
         using FT = std::remove_pointer_t<decltype(tag)>;
-        return with_q(q, 0, [&](auto qc) -> int {
+        return with_q<FT>(q, 0, [&](auto qc) -> int {
             constexpr int Q = decltype(qc)::value;
             return win ? cluster_capacity_t<FT, Q, true>(lds) : cluster_capacity_t<FT, Q, false>(lds);
         });
@@ -977,7 +1013,7 @@ hipError_t launch_sweep_cluster(int ft, int q, const LsmcArgs& a, const ClusterA
     if (!cluster_q_supported(q, ft)) return hipErrorInvalidValue;
     return with_feat(ft, hipErrorInvalidValue, [&](auto tag) -> hipError_t {
         using FT = std::remove_pointer_t<decltype(tag)>;
-        return with_q(q, hipErrorInvalidValue, [&](auto qc) -> hipError_t {
+        return with_q<FT>(q, hipErrorInvalidValue, [&](auto qc) -> hipError_t {
             constexpr int Q = decltype(qc)::value;
             return win ? launch_cluster_t<FT, Q, true>(a, c, S_launch, lds, st)
                        : launch_cluster_t<FT, Q, false>(a, c, S_launch, lds, st);

@@ -247,6 +247,20 @@ def test_bitwise_invariance_launch_shape_and_passes():
         assert rel(g["scenario_price"], ref["scenario_price"]).max() <= 1e-13
 
 
+@pytest.mark.parametrize("P", [140000, 157000, 175000])
+def test_cluster_sweep_wide_threads(P):
+    # FP32 features with 15 scenarios: the cluster sweep holds 18, 20 and 22
+    # paths per thread (16 workgroups per scenario, ragged last one); against
+    # the single-workgroup sweep with the state in the workspace on the same
+    # features, which adds the same FP64 terms in another order
+    _say("cluster sweep, wide threads, P=%d" % P)
+    w = W.best_of_call(n_assets=3, n_paths=P, n_steps=8)
+    g = gpu(w, "fp32")
+    b = gpu(w, "fp32", sweep_mode=2)
+    assert rel(g["scenario_price"], b["scenario_price"]).max() <= 1e-13
+    assert rel(g["scenario_se"], b["scenario_se"]).max() <= 1e-11
+
+
 def test_bitwise_invariance_fp64_16_asset_wave_cap():
     # FP64 at 13-16 assets runs at most 4 waves per block: asking for 8, or
     # fewer, gives the same features and so the same prices bit for bit
