@@ -385,9 +385,10 @@ Shape shape_of(const Request& q)
                                                           : kFeatF32;
     // cluster sweep shape from the request alone (never from device load, nor
     // from the workspace): spread the Greek set's scenarios over the compute
-    // units, from one path per thread up to the most that two workgroups per
-    // CU hold (a set larger than the device runs in several launches, each a
-    // chain of exchanges: more paths per thread, fewer launches)
+    // units, from one path per thread up to the most that one workgroup per
+    // CU holds in registers (a set larger than the device runs in several
+    // launches, each a chain of exchanges: more paths per thread, fewer
+    // launches)
     const int64_t P = q.P;
     const int64_t T = kClusterThreads;
     const int64_t S = num_scenarios(q.N, q.bumps.mask);
