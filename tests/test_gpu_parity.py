@@ -247,6 +247,20 @@ def test_bitwise_invariance_launch_shape_and_passes():
         assert rel(g["scenario_price"], ref["scenario_price"]).max() <= 1e-13
 
 
+@pytest.mark.parametrize("P", [20000, 25000])
+def test_cluster_sweep_fp64_five_and_six_paths(P):
+    # FP64 features, 28 scenarios, 8 or 9 workgroups per scenario: 5 paths per
+    # thread (two workgroups per CU) and 6 (one per CU: FP64 pairs need the
+    # larger register budget there); exercise dates identical to the oracle's
+    w = W.best_of_call(n_assets=5, n_paths=P, n_steps=16)
+    _say("cluster sweep FP64 P=%d" % P)
+    o = orc(w, export_tau=True)
+    g = gpu(w, "fp64", export_tau=True)
+    assert rel(g["scenario_price"], o["scenario_price"]).max() <= 1e-12
+    assert rel(g["scenario_se"], o["scenario_se"]).max() <= 1e-9
+    assert np.array_equal(g["tau"], o["tau"])
+
+
 @pytest.mark.parametrize("P", [140000, 157000, 175000])
 def test_cluster_sweep_wide_threads(P):
     # FP32 features with 15 scenarios: the cluster sweep holds 18, 20 and 22
