@@ -650,25 +650,31 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
     const int desired = (target_waves + pp.nchunks - 1) / pp.nchunks;
     G = std::max(G, std::min(desired, static_cast<int>(units.size()) + 1));
     if (q.opts.waves_per_block > 0) G = std::max(G, q.opts.waves_per_block);
-    std::vector<std::vector<int>> gs(G);
-    std::vector<int> load(G, 0), cnt(G, 0);
-    if (pass.has_base_spot) load[0] = std::max(1, N / 2);
-    for (int si : units) {
-        const int w = sc[si].hi - sc[si].lo;
-        int best = -1;
-        for (int g = 0; g < static_cast<int>(gs.size()); ++g)
-            if (cnt[g] + w <= tmax && (best < 0 || load[g] < load[best])) best = g;
-        if (best < 0) {
-            gs.emplace_back();
-            load.push_back(0);
-            cnt.push_back(0);
-            best = static_cast<int>(gs.size()) - 1;
+    // task scenarios into groups, one group per wave: heaviest first, each to
+    // the least-loaded group with room (a group past TMAX tasks opens another)
+    auto group = [&](int ng) {
+        std::vector<std::vector<int>> out(ng);
+        std::vector<int> load(ng, 0), cnt(ng, 0);
+        if (pass.has_base_spot) load[0] = std::max(1, N / 2);
+        for (int si : units) {
+            const int w = sc[si].hi - sc[si].lo;
+            int best = -1;
+            for (int g = 0; g < static_cast<int>(out.size()); ++g)
+                if (cnt[g] + w <= tmax && (best < 0 || load[g] < load[best])) best = g;
+            if (best < 0) {
+                out.emplace_back();
+                load.push_back(0);
+                cnt.push_back(0);
+                best = static_cast<int>(out.size()) - 1;
+            }
+            out[best].push_back(si);
+            load[best] += w;
+            cnt[best] += w;
         }
-        gs[best].push_back(si);
-        load[best] += w;
-        cnt[best] += w;
-    }
-    for (auto& v : gs) std::sort(v.begin(), v.end());
+        for (auto& v : out) std::sort(v.begin(), v.end());
+        return out;
+    };
+    std::vector<std::vector<int>> gs = group(G);
     const int vmax = paths_max_waves(sh.fp32, q.opts.scheme == HS_SCHEME_QE, sh.nmax);
     const int wcap = std::max(1, std::min(wmax > 0 ? wmax : vmax, vmax));
     int W = q.opts.waves_per_block > 0 ? q.opts.waves_per_block
@@ -684,6 +690,15 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
     W = std::min(W, vmax);
     pp.W = W;
     pp.nbg = static_cast<int>((gs.size() + W - 1) / W);
+    // the blocks of a path chunk have nbg W waves: spread the task scenarios
+    // over all of them rather than leave some waves without tasks (the same
+    // blocks, shorter task chains per wave; results do not depend on the
+    // grouping)
+    const int slots = pp.nbg * W;
+    if (static_cast<int>(gs.size()) < slots && static_cast<int>(units.size()) >= slots) {
+        std::vector<std::vector<int>> spread = group(slots);
+        if (static_cast<int>(spread.size()) == slots) gs = std::move(spread);
+    }
     // dates stored per scenario: all (American), a window of them, or the last
     pp.plane = (sh.american ? static_cast<int64_t>(pass.window > 0 ? pass.window : q.n) : 1) * q.P;
     if (sh.fp32)
