@@ -679,13 +679,14 @@ PassPlan plan_pass(const Request& q, const Shape& sh, const std::vector<Scenario
     const int wcap = std::max(1, std::min(wmax > 0 ? wmax : vmax, vmax));
     int W = q.opts.waves_per_block > 0 ? q.opts.waves_per_block
                                        : std::min(static_cast<int>(gs.size()), wcap);
-    // more task groups than a block holds: as few waves per block as the
-    // base assets allow, unless that is 5 or more (measured on 8-20 assets
-    // at 50k-200k paths: 3 or 4 waves per block run 30-42% faster than 8;
-    // 5 and 6 run slower than 8)
+    // more task groups than 8 waves hold: 4 waves per block where the base
+    // assets fit in 4, else 8 (measured on 8-20 assets at 50k-200k paths: 3
+    // or 4 waves per block run 30-42% faster than 8, 4 ahead of 3 at 10
+    // assets x 200k; 5 and 6 run slower than 8, and one block of 10 or more
+    // waves slower still)
     const int task_groups = (total + tmax - 1) / tmax;
-    if (q.opts.waves_per_block == 0 && wmax == 0 && task_groups > vmax)
-        W = wmin <= 4 ? wmin : 8;
+    if (q.opts.waves_per_block == 0 && wmax == 0 && task_groups > std::min(vmax, 8))
+        W = wmin <= 4 ? 4 : 8;
     W = std::max(W, wmin);
     W = std::min(W, vmax);
     pp.W = W;
